@@ -1,0 +1,185 @@
+/* ipibm.h -- C-ABI of the MI355X interaction-potential + immersed-boundary
+ * Lagrangian step (Spandan et al., "A parallel interaction potential approach
+ * coupled with the immersed boundary method for fully resolved simulations of
+ * deformable interfaces and membranes").
+ *
+ * One call = one pass of a step of the method over a batch of triangulated
+ * bodies: interaction-potential forces (Section 2.3), transfer between the
+ * Lagrangian nodes and the staggered Eulerian grid (Section 2.2) and the
+ * explicit node update (Section 2.3, Newton's second law per vertex).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Positions X are double[N][3] (row-major, node-major), always FP64.
+ * - "real" below is double for an IP_F64 plan and float for an IP_F32 plan.
+ *   In IP_F32 plans edge vectors are formed from the FP64 positions before
+ *   rounding, and the per-body volume, its reduction and the position update
+ *   stay FP64.
+ * - Node ids are int32 global indices into X.  Body b owns the nodes
+ *   [node_off[b], node_off[b+1]), edges [edge_off[b], edge_off[b+1]) and faces
+ *   [face_off[b], face_off[b+1]); every element of body b references only
+ *   nodes of body b.
+ * - Grid fields u (velocity) and f (force density) are real[3][nz][ny][nx],
+ *   x fastest: component d lives on the MAC lattice d, u_x at
+ *   (i, j+1/2, k+1/2) h, u_y at (i+1/2, j, k+1/2) h, u_z at (i+1/2, j+1/2, k) h
+ *   (Section 2.1 staggered grid; offsets are our reading).  The box
+ *   [0, nx h) x [0, ny h) x [0, nz h) is periodic in all directions.
+ * - All pointers passed to compute entry points are DEVICE pointers unless
+ *   marked "host".  The caller owns every array it passes; the plan owns only
+ *   what it derives (connectivity copies, gather lists, workspace).
+ * - Calls are asynchronous on `stream` (a hipStream_t, 0 = null stream).
+ *   Argument errors return synchronously with IP_ERR_ARG and launch nothing.
+ *   Device-detected conditions (degenerate element, non-finite value) set
+ *   bits of the plan's status word, read by ip_plan_status().
+ * - One plan may be used from one host thread at a time.  Calls on one plan
+ *   that overlap in time (different streams) race on its workspace.
+ */
+#ifndef IPIBM_H
+#define IPIBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ip_plan ip_plan;
+
+typedef enum {
+    IP_OK = 0,
+    IP_ERR_ARG = -1,          /* invalid argument; nothing launched */
+    IP_ERR_HIP = -2,          /* HIP runtime error (message in ip_last_error) */
+    IP_ERR_DEGENERATE = -3,   /* returned by ip_plan_status only */
+    IP_ERR_NONFINITE = -4,    /* returned by ip_plan_status only */
+    IP_ERR_OOM = -5,          /* device allocation failed */
+    IP_ERR_UNSUPPORTED = -6   /* valid request this build does not support */
+} ip_status;
+
+typedef enum { IP_F64 = 0, IP_F32 = 1 } ip_precision;
+
+/* Status-word bits (ip_plan_status). */
+#define IP_STATUS_DEGENERATE 0x1u  /* zero-length edge, zero-area face or hinge */
+#define IP_STATUS_NONFINITE  0x2u  /* a non-finite force or velocity was produced */
+
+/* Mesh of all bodies (Section 5 data structures: vertices of a face and the
+ * four vertices of the two faces sharing an edge).  Everything is HOST memory,
+ * read and copied during ip_plan_create only.
+ *   faces[F][3]   triangle vertices, counter-clockwise seen from outside.
+ *   edges4[E][4]  (v1, v2, v3, v4): (v1, v2) is the edge, v3 closes the face
+ *                 (v1, v2, v3), v4 closes the face (v2, v1, v4); -1 marks a
+ *                 missing face (open boundary: the edge keeps its spring but
+ *                 has no bending hinge).
+ *   closed[B]     1 = closed surface (volume potential applies), 0 = open.
+ *   pinned[N]     1 = node never moves (may be NULL = none pinned).
+ * Validation: offsets start at 0 and do not decrease; element nodes lie in
+ * their body; v1 != v2; faces have three distinct nodes. */
+typedef struct {
+    int32_t n_bodies;
+    const int64_t *node_off;
+    const int64_t *edge_off;
+    const int64_t *face_off;
+    const int32_t *faces;
+    const int32_t *edges4;
+    const uint8_t *closed;
+    const uint8_t *pinned;
+} ip_mesh;
+
+/* Periodic MAC grid: nx, ny, nz >= 3 cells of size h > 0. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double h;
+} ip_grid;
+
+/* Reference (stress-free) state, device arrays (Section 2.3: initial edge
+ * lengths, angles between adjacent faces, triangle areas, body volumes).
+ *   l0[E]      real   reference edge length
+ *   cs0[E][2]  real   (cos theta0, sin theta0) of the signed reference
+ *                     dihedral angle; (1, 0) on edges without a hinge
+ *   A0[F]      real   reference triangle area
+ *   V0[B]      double reference enclosed volume (closed bodies) */
+typedef struct {
+    const void *l0;
+    const void *cs0;
+    const void *A0;
+    const double *V0;
+} ip_reference;
+
+/* Per-body constants, device double[B] each (Section 2.3: k_e, k_b, k_a, k_v
+ * and the node mass m). */
+typedef struct {
+    const double *ks;
+    const double *kb;
+    const double *kA;
+    const double *kV;
+    const double *mass;
+} ip_constants;
+
+/* Build a plan: validates and copies the mesh, builds the node gather lists
+ * and allocates workspace for N nodes.  `grid` may be NULL for plans that only
+ * compute forces.  On success *plan is set; on failure it is left NULL. */
+ip_status ip_plan_create(ip_plan **plan, const ip_mesh *mesh, const ip_grid *grid,
+                         ip_precision precision);
+
+/* Release every resource of the plan (synchronizes the device). NULL is ok. */
+ip_status ip_plan_destroy(ip_plan *plan);
+
+/* Sizes: counts[0..3] = bodies, nodes, edges, faces. */
+ip_status ip_plan_sizes(const ip_plan *plan, int64_t counts[4]);
+
+/* Reference state from reference positions Xref[N][3] (Section 2.3 "initial
+ * (reference) state").  Writes l0[E], cs0[E][2], A0[F] (real) and V0[B]
+ * (double).  The signed angle follows the forces' convention: positive for a
+ * convex fold, measured from the normal of face (v1, v2, v3) to that of
+ * face (v2, v1, v4) about v2 - v1. */
+ip_status ip_reference_from(ip_plan *plan, const double *Xref, void *l0, void *cs0,
+                            void *A0, double *V0, void *stream);
+
+/* Interaction-potential forces at positions X (Section 2.3):
+ *   W_e = 1/2 ks (l - l0)^2               every edge
+ *   W_b = kb (1 - cos(theta - theta0))    every edge with two faces
+ *   W_a = 1/2 kA ((A - A0)/A0)^2 A0       every triangle
+ *   W_v = 1/2 kV ((V - V0)/V0)^2 V0       every closed body
+ * F = -grad(sum W) -> F[N][3] (real, overwritten).  V[B], A[B] (double,
+ * may be NULL) receive each body's enclosed volume and area; W[B][4]
+ * (double, may be NULL) the four energies (spring, bending, area, volume).
+ * Element results are gathered into nodes through per-node lists; no
+ * atomics, so F is bitwise reproducible. */
+ip_status ip_forces(ip_plan *plan, const double *X, const ip_reference *ref,
+                    const ip_constants *k, void *F, double *V, double *A, double *W,
+                    void *stream);
+
+/* Interpolation of the staggered velocity to the nodes with the 3-point
+ * regularised delta of Roma, Peskin & Berger (3x3x3 support, the support
+ * domain of Section 2.2): U_d(X_l) = sum_k u_d[k] phi phi phi.
+ * u: real[3][nz][ny][nx]; U: real[N][3] (overwritten).  Requires a grid. */
+ip_status ibm_interp(ip_plan *plan, const double *X, const void *u, void *U, void *stream);
+
+/* Spreading of nodal forces to the grid, the adjoint of ibm_interp up to h^3
+ * (Section 2.2: total force conserved): f_d[k] += sum_l F_{l,d} phi phi phi / h^3.
+ * F: real[N][3]; f: real[3][nz][ny][nx], ACCUMULATED (caller zeroes it).
+ * Uses device atomics on f: the summation order is not fixed. */
+ip_status ibm_spread(ip_plan *plan, const double *X, const void *F, void *f, void *stream);
+
+/* One explicit step (Section 2.3 Newton update, loosely coupled; the external
+ * load is the immersed-boundary reaction m (U - Xdot)/dt of Section 2.2's
+ * direct forcing, so that Xdot = U + (dt/m) F):
+ *   F = forces(X), U = interp(u, X), f += spread(F, X),
+ *   X <- X + dt U + (dt^2/m_b) F       for nodes that are not pinned.
+ * X is updated in place.  V[B], A[B] (may be NULL) receive the volumes and
+ * areas at the old positions.  f may be NULL (no spreading). */
+ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_constants *k,
+                  const void *u, void *f, double dt, double *V, double *A, void *stream);
+
+/* Wait for the plan's work on `stream`, read and clear the status word.
+ * Returns IP_OK, IP_ERR_DEGENERATE or IP_ERR_NONFINITE; *flags (may be NULL)
+ * receives the raw bits. */
+ip_status ip_plan_status(ip_plan *plan, void *stream, uint32_t *flags);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ip_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPIBM_H */

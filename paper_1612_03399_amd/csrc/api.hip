@@ -1,0 +1,300 @@
+// api.hip -- the C-ABI of libipibm: plan construction (validation, device copies
+// of the mesh, node gather lists, workspace) and the entry points declared in
+// include/ipibm.h.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ipibm_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename T>
+ip_status upload(T **dst, const T *src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return IP_OK;
+    hipError_t e = hipMalloc((void **)dst, n * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        ipibm_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return IP_ERR_OOM;
+    }
+    if (src) IP_HIP_CHECK(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return IP_OK;
+}
+
+ip_status alloc_bytes(void **dst, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return IP_OK;
+    hipError_t e = hipMalloc(dst, n);
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        ipibm_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return IP_ERR_OOM;
+    }
+    return IP_OK;
+}
+
+ip_status arg_error(const std::string &m) {
+    ipibm_set_error(m);
+    return IP_ERR_ARG;
+}
+
+#define IP_TRY(expr)                        \
+    do {                                    \
+        ip_status st_ = (expr);             \
+        if (st_ != IP_OK) return st_;       \
+    } while (0)
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+ip_status check_offsets(const int64_t *off, int B, const char *name) {
+    if (!off) return arg_error(std::string(name) + " is NULL");
+    if (off[0] != 0) return arg_error(std::string(name) + "[0] != 0");
+    for (int b = 0; b < B; ++b)
+        if (off[b + 1] < off[b]) return arg_error(std::string(name) + " decreases");
+    return IP_OK;
+}
+
+void free_plan(ip_plan *p) {
+    if (!p) return;
+    void *ptrs[] = {p->node_off, p->edge_off, p->face_off, p->faces, p->edges4, p->closed,
+                    p->pinned, p->csr_ptr, p->csr_slot, p->slots, p->Fbuf, p->Ubuf,
+                    p->Vbuf, p->Abuf, p->status};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_precision prec) {
+    const int B = m->n_bodies;
+    if (B < 0) return arg_error("n_bodies < 0");
+    if (prec != IP_F64 && prec != IP_F32) return arg_error("unknown precision");
+    IP_TRY(check_offsets(m->node_off, B, "node_off"));
+    IP_TRY(check_offsets(m->edge_off, B, "edge_off"));
+    IP_TRY(check_offsets(m->face_off, B, "face_off"));
+    const int64_t N = m->node_off[B], E = m->edge_off[B], F = m->face_off[B];
+    if (N >= INT32_MAX) return arg_error("more than 2^31-1 nodes");
+    if ((E > 0 && !m->edges4) || (F > 0 && !m->faces) || (B > 0 && !m->closed))
+        return arg_error("mesh array is NULL");
+    if (4 * E + 3 * F >= (int64_t)INT32_MAX)
+        return (ipibm_set_error("element slot count exceeds int32"), IP_ERR_UNSUPPORTED);
+    if (grid) {
+        if (grid->nx < 3 || grid->ny < 3 || grid->nz < 3 || !(grid->h > 0.0))
+            return arg_error("grid needs nx, ny, nz >= 3 and h > 0");
+        p->grid = *grid;
+        p->has_grid = true;
+    }
+    // element nodes must lie in their body
+    for (int b = 0; b < B; ++b) {
+        const int64_t n0 = m->node_off[b], n1 = m->node_off[b + 1];
+        if (m->closed[b] && n1 == n0) return arg_error("closed body without nodes");
+        auto inb = [&](int32_t v) { return v >= n0 && v < n1; };
+        for (int64_t e = m->edge_off[b]; e < m->edge_off[b + 1]; ++e) {
+            const int32_t *q = m->edges4 + 4 * e;
+            if (!inb(q[0]) || !inb(q[1]) || q[0] == q[1])
+                return arg_error("edges4 row " + std::to_string(e) + ": bad edge nodes");
+            for (int r = 2; r < 4; ++r)
+                if (q[r] != -1 && !inb(q[r]))
+                    return arg_error("edges4 row " + std::to_string(e) + ": bad wing");
+            if (m->closed[b] && (q[2] < 0 || q[3] < 0))
+                return arg_error("edges4 row " + std::to_string(e) +
+                                 ": boundary edge in a body marked closed");
+        }
+        for (int64_t f = m->face_off[b]; f < m->face_off[b + 1]; ++f) {
+            const int32_t *t = m->faces + 3 * f;
+            if (!inb(t[0]) || !inb(t[1]) || !inb(t[2]) || t[0] == t[1] || t[1] == t[2] ||
+                t[0] == t[2])
+                return arg_error("faces row " + std::to_string(f) + ": bad nodes");
+        }
+    }
+    p->B = B;
+    p->N = N;
+    p->E = E;
+    p->F = F;
+    p->prec = prec;
+    IP_HIP_CHECK(hipGetDevice(&p->device));
+    p->h_node_off.assign(m->node_off, m->node_off + B + 1);
+    p->h_edge_off.assign(m->edge_off, m->edge_off + B + 1);
+    p->h_face_off.assign(m->face_off, m->face_off + B + 1);
+
+    // node <- slot gather lists, slots ascending within each node
+    std::vector<int32_t> cnt(N + 1, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *q = m->edges4 + 4 * e;
+        const bool hinge = q[2] >= 0 && q[3] >= 0;
+        for (int r = 0; r < (hinge ? 4 : 2); ++r) ++cnt[q[r] + 1];
+    }
+    for (int64_t f = 0; f < F; ++f)
+        for (int c = 0; c < 3; ++c) ++cnt[m->faces[3 * f + c] + 1];
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> slot_ids(cnt[N]);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *q = m->edges4 + 4 * e;
+        const bool hinge = q[2] >= 0 && q[3] >= 0;
+        for (int r = 0; r < (hinge ? 4 : 2); ++r) slot_ids[fill[q[r]]++] = (int32_t)(4 * e + r);
+    }
+    for (int64_t f = 0; f < F; ++f)
+        for (int c = 0; c < 3; ++c)
+            slot_ids[fill[m->faces[3 * f + c]]++] = (int32_t)(4 * E + 3 * f + c);
+
+    std::vector<uint8_t> pin(N, 0);
+    if (m->pinned) std::copy(m->pinned, m->pinned + N, pin.begin());
+
+    IP_TRY(upload(&p->node_off, m->node_off, B + 1));
+    IP_TRY(upload(&p->edge_off, m->edge_off, B + 1));
+    IP_TRY(upload(&p->face_off, m->face_off, B + 1));
+    IP_TRY(upload(&p->faces, m->faces, 3 * F));
+    IP_TRY(upload(&p->edges4, m->edges4, 4 * E));
+    IP_TRY(upload(&p->closed, m->closed, B));
+    IP_TRY(upload(&p->pinned, pin.data(), N));
+    IP_TRY(upload(&p->csr_ptr, cnt.data(), N + 1));
+    IP_TRY(upload(&p->csr_slot, slot_ids.data(), slot_ids.size()));
+    const size_t rs = p->real_size();
+    IP_TRY(alloc_bytes(&p->slots, (size_t)(4 * E + 3 * F) * 3 * rs));
+    IP_TRY(alloc_bytes(&p->Fbuf, (size_t)N * 3 * rs));
+    IP_TRY(alloc_bytes(&p->Ubuf, (size_t)N * 3 * rs));
+    IP_TRY(upload(&p->Vbuf, (const double *)nullptr, B));
+    IP_TRY(upload(&p->Abuf, (const double *)nullptr, B));
+    IP_TRY(upload(&p->status, (const uint32_t *)nullptr, 1));
+    IP_HIP_CHECK(hipMemset(p->status, 0, sizeof(uint32_t)));
+    IP_HIP_CHECK(hipDeviceSynchronize());
+    return IP_OK;
+}
+
+ip_status check_plan(const ip_plan *p) {
+    if (!p) return arg_error("plan is NULL");
+    int dev = -1;
+    IP_HIP_CHECK(hipGetDevice(&dev));
+    if (dev != p->device) return arg_error("current device differs from the plan's device");
+    return IP_OK;
+}
+
+ip_status check_ref_k(const ip_plan *p, const ip_reference *ref, const ip_constants *k,
+                      bool need_mass) {
+    if (!ref || !k) return arg_error("reference or constants is NULL");
+    if ((p->E > 0 && (!ref->l0 || !ref->cs0)) || (p->F > 0 && !ref->A0) ||
+        (p->B > 0 && !ref->V0))
+        return arg_error("reference array is NULL");
+    if (p->B > 0 && (!k->ks || !k->kb || !k->kA || !k->kV || (need_mass && !k->mass)))
+        return arg_error("constant array is NULL");
+    const size_t rs = p->real_size();
+    if (!aligned(ref->l0, rs) || !aligned(ref->cs0, rs) || !aligned(ref->A0, rs) ||
+        !aligned(ref->V0, 8))
+        return arg_error("misaligned reference array");
+    return IP_OK;
+}
+
+}  // namespace
+
+void ipibm_set_error(const std::string &msg) { g_last_error = msg; }
+
+extern "C" {
+
+const char *ip_last_error(void) { return g_last_error.c_str(); }
+
+ip_status ip_plan_create(ip_plan **plan, const ip_mesh *mesh, const ip_grid *grid,
+                         ip_precision precision) {
+    if (!plan) return arg_error("plan out-pointer is NULL");
+    *plan = nullptr;
+    if (!mesh) return arg_error("mesh is NULL");
+    ip_plan *p = new ip_plan();
+    ip_status st = build_plan(p, mesh, grid, precision);
+    if (st != IP_OK) {
+        free_plan(p);
+        return st;
+    }
+    *plan = p;
+    return IP_OK;
+}
+
+ip_status ip_plan_destroy(ip_plan *plan) {
+    if (!plan) return IP_OK;
+    (void)hipDeviceSynchronize();
+    free_plan(plan);
+    return IP_OK;
+}
+
+ip_status ip_plan_sizes(const ip_plan *plan, int64_t counts[4]) {
+    if (!plan || !counts) return arg_error("NULL argument");
+    counts[0] = plan->B;
+    counts[1] = plan->N;
+    counts[2] = plan->E;
+    counts[3] = plan->F;
+    return IP_OK;
+}
+
+ip_status ip_reference_from(ip_plan *plan, const double *Xref, void *l0, void *cs0, void *A0,
+                            double *V0, void *stream) {
+    IP_TRY(check_plan(plan));
+    if ((plan->N > 0 && !Xref) || (plan->E > 0 && (!l0 || !cs0)) || (plan->F > 0 && !A0) ||
+        (plan->B > 0 && !V0))
+        return arg_error("NULL array");
+    if (!aligned(Xref, 8)) return arg_error("misaligned X");
+    hipStream_t s = (hipStream_t)stream;
+    IP_TRY(launch_geometry(plan, Xref, V0, plan->Abuf, s));
+    return launch_reference(plan, Xref, l0, cs0, A0, s);
+}
+
+ip_status ip_forces(ip_plan *plan, const double *X, const ip_reference *ref,
+                    const ip_constants *k, void *F, double *V, double *A, double *W,
+                    void *stream) {
+    IP_TRY(check_plan(plan));
+    IP_TRY(check_ref_k(plan, ref, k, false));
+    if (plan->N > 0 && (!X || !F)) return arg_error("X or F is NULL");
+    if (!aligned(X, 8) || !aligned(F, plan->real_size())) return arg_error("misaligned X or F");
+    return launch_forces(plan, X, ref, k, F, V, A, W, (hipStream_t)stream);
+}
+
+ip_status ibm_interp(ip_plan *plan, const double *X, const void *u, void *U, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (plan->N > 0 && (!X || !u || !U)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(u, plan->real_size()) || !aligned(U, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_interp(plan, X, u, U, (hipStream_t)stream);
+}
+
+ip_status ibm_spread(ip_plan *plan, const double *X, const void *F, void *f, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (plan->N > 0 && (!X || !F || !f)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(F, plan->real_size()) || !aligned(f, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_spread(plan, X, F, f, (hipStream_t)stream);
+}
+
+ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_constants *k,
+                  const void *u, void *f, double dt, double *V, double *A, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    IP_TRY(check_ref_k(plan, ref, k, true));
+    if (plan->N > 0 && (!X || !u)) return arg_error("X or u is NULL");
+    if (!aligned(X, 8) || !aligned(u, plan->real_size()) || !aligned(f, plan->real_size()))
+        return arg_error("misaligned array");
+    if (!(dt == dt)) return arg_error("dt is NaN");
+    hipStream_t s = (hipStream_t)stream;
+    IP_TRY(launch_forces(plan, X, ref, k, plan->Fbuf, V, A, nullptr, s));
+    IP_TRY(launch_interp(plan, X, u, plan->Ubuf, s));
+    if (f) IP_TRY(launch_spread(plan, X, plan->Fbuf, f, s));
+    return launch_update(plan, X, plan->Ubuf, plan->Fbuf, k, dt, s);
+}
+
+ip_status ip_plan_status(ip_plan *plan, void *stream, uint32_t *flags) {
+    IP_TRY(check_plan(plan));
+    uint32_t v = 0;
+    hipStream_t s = (hipStream_t)stream;
+    IP_HIP_CHECK(hipMemcpyAsync(&v, plan->status, sizeof(v), hipMemcpyDeviceToHost, s));
+    IP_HIP_CHECK(hipStreamSynchronize(s));
+    IP_HIP_CHECK(hipMemsetAsync(plan->status, 0, sizeof(uint32_t), s));
+    IP_HIP_CHECK(hipStreamSynchronize(s));
+    if (flags) *flags = v;
+    if (v & IP_STATUS_NONFINITE) return IP_ERR_NONFINITE;
+    if (v & IP_STATUS_DEGENERATE) return IP_ERR_DEGENERATE;
+    return IP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+// ipibm_internal.h -- plan object and device helpers shared by the HIP sources
+// of libipibm (gfx950).  Not part of the public C-ABI (include/ipibm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ipibm.h"
+
+// ----------------------------------------------------------------------------
+// error plumbing
+// ----------------------------------------------------------------------------
+void ipibm_set_error(const std::string &msg);
+
+#define IP_HIP_CHECK(expr)                                                        \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ipibm_set_error(std::string(#expr) + ": " + hipGetErrorString(e_));   \
+            return IP_ERR_HIP;                                                    \
+        }                                                                         \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// plan
+// ----------------------------------------------------------------------------
+struct ip_plan {
+    int32_t B = 0;
+    int64_t N = 0, E = 0, F = 0;
+    ip_precision prec = IP_F64;
+    bool has_grid = false;
+    ip_grid grid{};
+    int device = 0;
+
+    std::vector<int64_t> h_node_off, h_edge_off, h_face_off;
+
+    // device copies of the mesh
+    int64_t *node_off = nullptr, *edge_off = nullptr, *face_off = nullptr;
+    int32_t *faces = nullptr;    // [F][3]
+    int32_t *edges4 = nullptr;   // [E][4]
+    uint8_t *closed = nullptr;   // [B]
+    uint8_t *pinned = nullptr;   // [N]
+
+    // node <- element-slot gather lists (CSR), slot id = 4 e + role for edges,
+    // 4 E + 3 f + corner for faces
+    int32_t *csr_ptr = nullptr;   // [N+1]
+    int32_t *csr_slot = nullptr;  // [csr_ptr[N]]
+
+    // workspace
+    void *slots = nullptr;        // [(4E + 3F)][3] real
+    void *Fbuf = nullptr;         // [N][3] real
+    void *Ubuf = nullptr;         // [N][3] real
+    double *Vbuf = nullptr;       // [B]
+    double *Abuf = nullptr;       // [B]
+    uint32_t *status = nullptr;   // device status word
+
+    size_t real_size() const { return prec == IP_F64 ? sizeof(double) : sizeof(float); }
+};
+
+// launchers (k_forces.hip / k_transfer.hip); all asynchronous on `s`
+ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s);
+ip_status launch_reference(ip_plan *p, const double *Xref, void *l0, void *cs0, void *A0,
+                           hipStream_t s);
+ip_status launch_forces(ip_plan *p, const double *X, const ip_reference *ref,
+                        const ip_constants *k, void *F, double *V, double *A, double *W,
+                        hipStream_t s);
+ip_status launch_interp(ip_plan *p, const double *X, const void *u, void *U, hipStream_t s);
+ip_status launch_spread(ip_plan *p, const double *X, const void *F, void *f, hipStream_t s);
+ip_status launch_update(ip_plan *p, double *X, const void *U, const void *F,
+                        const ip_constants *k, double dt, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// device helpers
+// ----------------------------------------------------------------------------
+template <typename R>
+struct vec3 {
+    R x, y, z;
+};
+
+template <typename R>
+__device__ __forceinline__ vec3<R> operator-(vec3<R> a, vec3<R> b) {
+    return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <typename R>
+__device__ __forceinline__ vec3<R> operator+(vec3<R> a, vec3<R> b) {
+    return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+template <typename R>
+__device__ __forceinline__ vec3<R> operator*(R s, vec3<R> a) {
+    return {s * a.x, s * a.y, s * a.z};
+}
+template <typename R>
+__device__ __forceinline__ R dot(vec3<R> a, vec3<R> b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename R>
+__device__ __forceinline__ vec3<R> cross(vec3<R> a, vec3<R> b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+// difference of two FP64 points, rounded once to R
+template <typename R>
+__device__ __forceinline__ vec3<R> diffR(const vec3<double> &a, const vec3<double> &b) {
+    return {(R)(a.x - b.x), (R)(a.y - b.y), (R)(a.z - b.z)};
+}
+__device__ __forceinline__ vec3<double> ldX(const double *X, int64_t i) {
+    const double *p = X + 3 * i;
+    return {p[0], p[1], p[2]};
+}
+
+// Index of the body owning element/node i: the last b with off[b] <= i.
+__device__ __forceinline__ int body_of(const int64_t *off, int B, int64_t i) {
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  `sh` holds
+// blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < (blockDim.x >> 6)) r = sh[threadIdx.x];
+    if (w == 0) r = wave_sum(r);
+    return r;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    int m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+// Weights of the 3-point regularised delta (Roma, Peskin & Berger) at the three
+// lattice points nearest to the fractional lattice coordinate s: c = floor(s+1/2),
+// r = s - c in [-1/2, 1/2], q = sqrt(1 - 3 r^2):
+//   w[0] (point c-1) = (2 - 3r - q)/6, w[1] (point c) = (1 + q)/3,
+//   w[2] (point c+1) = (2 + 3r - q)/6.
+// Returns c.
+template <typename R>
+__device__ __forceinline__ int delta3(double s, R w[3]) {
+    double c = floor(s + 0.5);
+    if (!(fabs(c) < 1.0e9)) c = 0.0;   // non-finite or absurd position: stay in bounds
+    const R r = (R)(s - c);
+    const R q = sqrt((R)1 - (R)3 * r * r);
+    w[0] = ((R)2 - (R)3 * r - q) * (R)(1.0 / 6.0);
+    w[1] = ((R)1 + q) * (R)(1.0 / 3.0);
+    w[2] = ((R)2 + (R)3 * r - q) * (R)(1.0 / 6.0);
+    return (int)c;
+}
+
+// MAC lattice offsets (cells): lattice d has offset 0 along axis d, 1/2 along
+// the two others.
+__device__ __forceinline__ double mac_off(int d, int axis) { return d == axis ? 0.0 : 0.5; }

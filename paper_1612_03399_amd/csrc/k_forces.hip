@@ -1,0 +1,359 @@
+// k_forces.hip -- interaction-potential forces (Section 2.3 of Spandan et al.):
+// per-body geometry reductions, per-edge spring + bending hinge, per-face area +
+// volume-gradient, and the scatter-free gather of element results into nodes.
+#include <cmath>
+
+#include "ipibm_internal.h"
+
+namespace {
+
+constexpr int kGeomThreads = 256;
+constexpr int kElemThreads = 256;
+
+// ----------------------------------------------------------------------------
+// Per-body area A_b = sum |n_f|/2 and enclosed volume
+// V_b = (1/6) sum_f (x_i - a).((x_j - a) x (x_k - a)), a = first node of the
+// body (divergence theorem).  One workgroup per body; FP64 accumulation and a
+// fixed-shape tree reduction (wave shuffles, then LDS), so the result does not
+// depend on scheduling.
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kGeomThreads) void k_geometry(
+    const double *__restrict__ X, const int32_t *__restrict__ faces,
+    const int64_t *__restrict__ node_off, const int64_t *__restrict__ face_off,
+    double *__restrict__ V, double *__restrict__ A) {
+    __shared__ double sh[kGeomThreads / 64];
+    const int b = blockIdx.x;
+    if (face_off[b] == face_off[b + 1]) {   // no faces: the body may own no node
+        if (threadIdx.x == 0) V[b] = A[b] = 0.0;
+        return;
+    }
+    const vec3<double> a = ldX(X, node_off[b]);
+    double vs = 0.0, as = 0.0;
+    for (int64_t f = face_off[b] + threadIdx.x; f < face_off[b + 1]; f += blockDim.x) {
+        const int32_t *t = faces + 3 * f;
+        const vec3<double> xi = ldX(X, t[0]), xj = ldX(X, t[1]), xk = ldX(X, t[2]);
+        const vec3<double> ri = xi - a, rj = xj - a, rk = xk - a;
+        vs += dot(ri, cross(rj, rk));
+        const vec3<R> n = cross(diffR<R>(xj, xi), diffR<R>(xk, xi));
+        as += (double)sqrt(dot(n, n));
+    }
+    vs = block_sum(vs, sh);
+    as = block_sum(as, sh);
+    if (threadIdx.x == 0) {
+        V[b] = vs * (1.0 / 6.0);
+        A[b] = 0.5 * as;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Reference state: l0 per edge, (cos, sin) of the signed dihedral per edge,
+// A0 per face.  Computed in FP64 and rounded once to R.
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ void k_reference_edges(const double *__restrict__ X, const int4 *__restrict__ e4,
+                                  int64_t E, R *__restrict__ l0, R *__restrict__ cs0) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int4 q = e4[e];
+    const vec3<double> x1 = ldX(X, q.x), x2 = ldX(X, q.y);
+    const vec3<double> ev = x2 - x1;
+    const double le = sqrt(dot(ev, ev));
+    l0[e] = (R)le;
+    double c = 1.0, s = 0.0;
+    if (q.z >= 0 && q.w >= 0) {
+        const vec3<double> nA = cross(ev, ldX(X, q.z) - x1);
+        const vec3<double> nB = cross(ldX(X, q.w) - x1, ev);
+        const double inv = 1.0 / sqrt(dot(nA, nA) * dot(nB, nB));
+        c = dot(nA, nB) * inv;
+        s = dot(cross(nA, nB), ev) * inv / le;
+    }
+    cs0[2 * e] = (R)c;
+    cs0[2 * e + 1] = (R)s;
+}
+
+template <typename R>
+__global__ void k_reference_faces(const double *__restrict__ X, const int32_t *__restrict__ faces,
+                                  int64_t F, R *__restrict__ A0) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int32_t *t = faces + 3 * f;
+    const vec3<double> xi = ldX(X, t[0]);
+    const vec3<double> n = cross(ldX(X, t[1]) - xi, ldX(X, t[2]) - xi);
+    A0[f] = (R)(0.5 * sqrt(dot(n, n)));
+}
+
+// ----------------------------------------------------------------------------
+// Edge elements.  Spring W_e = 1/2 ks (l - l0)^2 on every edge and bending
+// hinge W_b = kb (1 - cos(theta - theta0)) where both wings exist.
+//
+// Hinge (v1, v2 | v3, v4), e = x2 - x1, nA = e x (x3 - x1), nB = (x4 - x1) x e,
+// |nA||nB| cos(theta) = nA.nB, |nA||nB| sin(theta) = (nA x nB).e / |e|.
+// dW/dtheta = kb sin(theta - theta0) = kb (sin c0 - cos s0).  The angle's
+// gradient: the wings move along their face normals,
+//   dtheta/dx3 = -|e| nA / |nA|^2,  dtheta/dx4 = -|e| nB / |nB|^2,
+// and the edge nodes take the unique combination that keeps theta invariant
+// under translation and rotation: with s3 = (x3-x1).e/|e|^2, s4 likewise,
+//   dtheta/dx1 = -(1-s3) dtheta/dx3 - (1-s4) dtheta/dx4,
+//   dtheta/dx2 = -s3 dtheta/dx3 - s4 dtheta/dx4.
+// The angle itself (normals, cos, sin, dW/dtheta) is always evaluated in FP64:
+// on fine smooth meshes theta - theta0 is ~1e-3 while FP32 edge vectors leave an
+// absolute error of ~1e-7 in sin(theta), which would cost FP32 plans four
+// digits of the bending force.  The force vectors are then formed in R.
+// Output: 4 slot vectors per edge (forces on v1..v4).
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kElemThreads) void k_edges(
+    const double *__restrict__ X, const int4 *__restrict__ e4,
+    const int64_t *__restrict__ edge_off, int B, int64_t E, const R *__restrict__ l0,
+    const R *__restrict__ cs0, const double *__restrict__ ks, const double *__restrict__ kb,
+    R *__restrict__ slots, uint32_t *__restrict__ status) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int b = body_of(edge_off, B, e);
+    const int4 q = e4[e];
+    const vec3<double> x1 = ldX(X, q.x), x2 = ldX(X, q.y);
+    const vec3<R> ev = diffR<R>(x2, x1);
+    const R le2 = dot(ev, ev);
+    const R le = sqrt(le2);
+    const R fs = (R)ks[b] * (le - l0[e]) / le;
+    vec3<R> f1 = fs * ev;
+    vec3<R> f2 = (R)-1 * f1;
+    vec3<R> f3 = {0, 0, 0}, f4 = {0, 0, 0};
+    bool bad = !(le > (R)0);
+    if (q.z >= 0 && q.w >= 0) {
+        const vec3<double> x3 = ldX(X, q.z), x4 = ldX(X, q.w);
+        const vec3<double> evd = x2 - x1, d3d = x3 - x1, d4d = x4 - x1;
+        const vec3<double> nA = cross(evd, d3d);
+        const vec3<double> nB = cross(d4d, evd);
+        const double nA2 = dot(nA, nA), nB2 = dot(nB, nB);
+        bad |= !(nA2 > 0.0) || !(nB2 > 0.0);
+        const double led = sqrt(dot(evd, evd));
+        const double inv = 1.0 / sqrt(nA2 * nB2);
+        const double cth = dot(nA, nB) * inv;
+        const double sth = dot(cross(nA, nB), evd) * inv / led;
+        const double c0 = (double)cs0[2 * e], s0 = (double)cs0[2 * e + 1];
+        const double dW = kb[b] * (sth * c0 - cth * s0);
+        // F3 = -dW dtheta/dx3 = dW |e| nA/|nA|^2, F4 likewise
+        const R a3 = (R)(dW * led / nA2), a4 = (R)(dW * led / nB2);
+        f3 = a3 * vec3<R>{(R)nA.x, (R)nA.y, (R)nA.z};
+        f4 = a4 * vec3<R>{(R)nB.x, (R)nB.y, (R)nB.z};
+        const vec3<R> d3 = diffR<R>(x3, x1), d4 = diffR<R>(x4, x1);
+        const R s3 = dot(d3, ev) / le2, s4 = dot(d4, ev) / le2;
+        f1 = f1 - ((R)1 - s3) * f3 - ((R)1 - s4) * f4;
+        f2 = f2 - s3 * f3 - s4 * f4;
+    }
+    if (bad) atomicOr(status, IP_STATUS_DEGENERATE);
+    R *o = slots + 12 * e;
+    o[0] = f1.x; o[1] = f1.y; o[2] = f1.z;
+    o[3] = f2.x; o[4] = f2.y; o[5] = f2.z;
+    o[6] = f3.x; o[7] = f3.y; o[8] = f3.z;
+    o[9] = f4.x; o[10] = f4.y; o[11] = f4.z;
+}
+
+// ----------------------------------------------------------------------------
+// Face elements: area W_a = 1/2 kA (A - A0)^2 / A0 with dA/dx_i = 1/2 nhat x
+// (x_k - x_j) (cyclic), and, on closed bodies, the volume potential
+// W_v = 1/2 kV (V - V0)^2 / V0 (V from k_geometry).  Differentiating the
+// divergence-theorem volume gives dV/dx_i = (1/6) sum_{f ni i} (x_j - a) x (x_k - a)
+// for any anchor a; around the closed fan of node i the anchor terms cancel,
+// and taking a = x_i leaves dV/dx_i = (1/6) sum_{f ni i} n_f: every face hands
+// n_f / 6 to each of its corners.  This form has no anchor cancellation (the
+// anchored terms are ~|x - a| |edge| while their sum is ~|edge|^2).
+// Output: 3 slot vectors per face (forces on its corners).
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kElemThreads) void k_faces(
+    const double *__restrict__ X, const int32_t *__restrict__ faces,
+    const int64_t *__restrict__ face_off, const int64_t *__restrict__ node_off, int B,
+    int64_t F, const R *__restrict__ A0, const double *__restrict__ V0,
+    const double *__restrict__ Vcur, const uint8_t *__restrict__ closed,
+    const double *__restrict__ kA, const double *__restrict__ kV, R *__restrict__ slots,
+    uint32_t *__restrict__ status) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int b = body_of(face_off, B, f);
+    const int32_t *t = faces + 3 * f;
+    const vec3<double> xi = ldX(X, t[0]), xj = ldX(X, t[1]), xk = ldX(X, t[2]);
+    const vec3<R> n = cross(diffR<R>(xj, xi), diffR<R>(xk, xi));
+    const R nn = sqrt(dot(n, n));
+    if (!(nn > (R)0)) atomicOr(status, IP_STATUS_DEGENERATE);
+    const R a0 = A0[f];
+    const R cA = (R)kA[b] * ((R)0.5 * nn - a0) / a0;   // dW_a/dA
+    // -cA * 1/2 nhat x edge  =  (-cA / (2|n|)) n x edge
+    const R sA = -cA / ((R)2 * nn);
+    vec3<R> gi = sA * cross(n, diffR<R>(xk, xj));
+    vec3<R> gj = sA * cross(n, diffR<R>(xi, xk));
+    vec3<R> gk = sA * cross(n, diffR<R>(xj, xi));
+    if (closed[b]) {
+        const double v0 = V0[b];
+        const R sV = (R)(-(double)kV[b] * (Vcur[b] - v0) / v0 * (1.0 / 6.0));
+        const vec3<R> gv = sV * n;
+        gi = gi + gv;
+        gj = gj + gv;
+        gk = gk + gv;
+    }
+    R *o = slots + 9 * f;
+    o[0] = gi.x; o[1] = gi.y; o[2] = gi.z;
+    o[3] = gj.x; o[4] = gj.y; o[5] = gj.z;
+    o[6] = gk.x; o[7] = gk.y; o[8] = gk.z;
+}
+
+// ----------------------------------------------------------------------------
+// Node gather: F_i = sum of the node's element slots, in ascending slot order
+// (deterministic, no atomics).
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ void k_gather(const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot_ids,
+                         const R *__restrict__ slots, int64_t N, R *__restrict__ F,
+                         uint32_t *__restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    R fx = 0, fy = 0, fz = 0;
+    for (int32_t s = ptr[i]; s < ptr[i + 1]; ++s) {
+        const R *v = slots + 3 * (int64_t)slot_ids[s];
+        fx += v[0];
+        fy += v[1];
+        fz += v[2];
+    }
+    if (!isfinite(fx) || !isfinite(fy) || !isfinite(fz)) atomicOr(status, IP_STATUS_NONFINITE);
+    F[3 * i] = fx;
+    F[3 * i + 1] = fy;
+    F[3 * i + 2] = fz;
+}
+
+// ----------------------------------------------------------------------------
+// Per-body energies W[b][4] = (spring, bending, area, volume); one workgroup
+// per body, evaluated and accumulated in FP64 for every plan precision (the
+// energies are diagnostics, off the step).  Only launched when W is requested.
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kGeomThreads) void k_energy(
+    const double *__restrict__ X, const int4 *__restrict__ e4, const int32_t *__restrict__ faces,
+    const int64_t *__restrict__ edge_off, const int64_t *__restrict__ face_off,
+    const R *__restrict__ l0, const R *__restrict__ cs0, const R *__restrict__ A0,
+    const double *__restrict__ V0, const double *__restrict__ Vcur,
+    const uint8_t *__restrict__ closed, const double *__restrict__ ks,
+    const double *__restrict__ kb, const double *__restrict__ kA,
+    const double *__restrict__ kV, double *__restrict__ W) {
+    __shared__ double sh[kGeomThreads / 64];
+    const int b = blockIdx.x;
+    double ws = 0.0, wb = 0.0, wa = 0.0;
+    for (int64_t e = edge_off[b] + threadIdx.x; e < edge_off[b + 1]; e += blockDim.x) {
+        const int4 q = e4[e];
+        const vec3<double> x1 = ldX(X, q.x);
+        const vec3<double> ev = ldX(X, q.y) - x1;
+        const double dl = sqrt(dot(ev, ev)) - (double)l0[e];
+        ws += dl * dl;
+        if (q.z >= 0 && q.w >= 0) {
+            const vec3<double> nA = cross(ev, ldX(X, q.z) - x1);
+            const vec3<double> nB = cross(ldX(X, q.w) - x1, ev);
+            const double inv = 1.0 / sqrt(dot(nA, nA) * dot(nB, nB));
+            const double cth = dot(nA, nB) * inv;
+            const double sth = dot(cross(nA, nB), ev) * inv / sqrt(dot(ev, ev));
+            // cos and sin of theta - theta0 (the stored pair renormalised, which
+            // matters once it has been rounded to FP32); 1 - cos d = sin^2 d /
+            // (1 + cos d) avoids the cancellation near the reference state
+            const double c0 = (double)cs0[2 * e], s0 = (double)cs0[2 * e + 1];
+            const double r0 = 1.0 / sqrt(c0 * c0 + s0 * s0);
+            const double cd = (cth * c0 + sth * s0) * r0, sd = (sth * c0 - cth * s0) * r0;
+            wb += cd > 0.0 ? sd * sd / (1.0 + cd) : 1.0 - cd;
+        }
+    }
+    for (int64_t f = face_off[b] + threadIdx.x; f < face_off[b + 1]; f += blockDim.x) {
+        const int32_t *t = faces + 3 * f;
+        const vec3<double> xi = ldX(X, t[0]);
+        const vec3<double> n = cross(ldX(X, t[1]) - xi, ldX(X, t[2]) - xi);
+        const double a0 = (double)A0[f];
+        const double da = 0.5 * sqrt(dot(n, n)) - a0;
+        wa += da * da / a0;
+    }
+    ws = block_sum(ws, sh);
+    wb = block_sum(wb, sh);
+    wa = block_sum(wa, sh);
+    if (threadIdx.x == 0) {
+        double wv = 0.0;
+        if (closed[b]) {
+            const double dv = Vcur[b] - V0[b];
+            wv = 0.5 * kV[b] * dv * dv / V0[b];
+        }
+        W[4 * b + 0] = 0.5 * ks[b] * ws;
+        W[4 * b + 1] = kb[b] * wb;
+        W[4 * b + 2] = 0.5 * kA[b] * wa;
+        W[4 * b + 3] = wv;
+    }
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename R>
+ip_status forces_impl(ip_plan *p, const double *X, const ip_reference *ref,
+                      const ip_constants *k, void *Fv, double *V, double *A, double *W,
+                      hipStream_t s) {
+    R *slots = (R *)p->slots;
+    double *Vb = V ? V : p->Vbuf;
+    double *Ab = A ? A : p->Abuf;
+    if (p->B > 0)
+        hipLaunchKernelGGL(k_geometry<R>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
+                           p->node_off, p->face_off, Vb, Ab);
+    if (p->E > 0)
+        hipLaunchKernelGGL(k_edges<R>, dim3(nblocks(p->E, kElemThreads)), dim3(kElemThreads), 0,
+                           s, X, (const int4 *)p->edges4, p->edge_off, p->B, p->E,
+                           (const R *)ref->l0, (const R *)ref->cs0, k->ks, k->kb, slots,
+                           p->status);
+    if (p->F > 0)
+        hipLaunchKernelGGL(k_faces<R>, dim3(nblocks(p->F, kElemThreads)), dim3(kElemThreads), 0,
+                           s, X, p->faces, p->face_off, p->node_off, p->B, p->F,
+                           (const R *)ref->A0, ref->V0, Vb, p->closed, k->kA, k->kV,
+                           slots + 12 * p->E, p->status);
+    if (p->N > 0)
+        hipLaunchKernelGGL(k_gather<R>, dim3(nblocks(p->N, 256)), dim3(256), 0, s, p->csr_ptr,
+                           p->csr_slot, slots, p->N, (R *)Fv, p->status);
+    if (W && p->B > 0)
+        hipLaunchKernelGGL(k_energy<R>, dim3(p->B), dim3(kGeomThreads), 0, s, X,
+                           (const int4 *)p->edges4, p->faces, p->edge_off, p->face_off,
+                           (const R *)ref->l0, (const R *)ref->cs0, (const R *)ref->A0, ref->V0,
+                           Vb, p->closed, k->ks, k->kb, k->kA, k->kV, W);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
+
+template <typename R>
+ip_status reference_impl(ip_plan *p, const double *X, void *l0, void *cs0, void *A0,
+                         hipStream_t s) {
+    if (p->E > 0)
+        hipLaunchKernelGGL(k_reference_edges<R>, dim3(nblocks(p->E, 256)), dim3(256), 0, s, X,
+                           (const int4 *)p->edges4, p->E, (R *)l0, (R *)cs0);
+    if (p->F > 0)
+        hipLaunchKernelGGL(k_reference_faces<R>, dim3(nblocks(p->F, 256)), dim3(256), 0, s, X,
+                           p->faces, p->F, (R *)A0);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
+
+}  // namespace
+
+ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s) {
+    if (p->B == 0) return IP_OK;
+    if (p->prec == IP_F64)
+        hipLaunchKernelGGL(k_geometry<double>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
+                           p->node_off, p->face_off, V, A);
+    else
+        hipLaunchKernelGGL(k_geometry<float>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
+                           p->node_off, p->face_off, V, A);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
+
+ip_status launch_reference(ip_plan *p, const double *Xref, void *l0, void *cs0, void *A0,
+                           hipStream_t s) {
+    return p->prec == IP_F64 ? reference_impl<double>(p, Xref, l0, cs0, A0, s)
+                             : reference_impl<float>(p, Xref, l0, cs0, A0, s);
+}
+
+ip_status launch_forces(ip_plan *p, const double *X, const ip_reference *ref,
+                        const ip_constants *k, void *F, double *V, double *A, double *W,
+                        hipStream_t s) {
+    return p->prec == IP_F64 ? forces_impl<double>(p, X, ref, k, F, V, A, W, s)
+                             : forces_impl<float>(p, X, ref, k, F, V, A, W, s);
+}

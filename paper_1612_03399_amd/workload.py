@@ -252,6 +252,10 @@ def _assemble(bodies, name, grid, dt, steps, precision, consts, mass=1.0):
         closed.append(1 if b["closed"] else 0)
     B = len(bodies)
     ks, kb, kA, kV = consts
+    if B == 0:
+        Xs, Xr = [np.zeros((0, 3))], [np.zeros((0, 3))]
+        Fs, Es = [np.zeros((0, 3), np.int32)], [np.zeros((0, 4), np.int32)]
+        pins = [np.zeros(0, np.uint8)]
     return Workload(
         name=name,
         X=np.ascontiguousarray(np.concatenate(Xs)),
@@ -382,7 +386,7 @@ def config2(n_bodies=4096, n=512):
     return wl
 
 
-def config3(freq=100, leaflet_quads=100, noise_rel=0.0):
+def config3(freq=100, leaflet_quads=100, noise_rel=0.0, cells_per_unit=256):
     """Ventricle-like membranes: closed prolate ellipsoidal shell (semi-axes
     0.3, 0.3, 0.8; geodesic frequency 100 -> 200 000 triangles) centred in a
     1.5 x 1.5 x 2.0 box (384 x 384 x 512, h = 1/256), plus two open flat
@@ -390,8 +394,8 @@ def config3(freq=100, leaflet_quads=100, noise_rel=0.0):
     their top edge at z = 1.6; the top row of each leaflet is pinned.  The
     velocity is an axial Gaussian jet plus random-Fourier noise."""
     place, noise, _, _ = _streams(3)
-    h = 1.0 / 256
-    grid = Grid(384, 384, 512, h)
+    h = 1.0 / cells_per_unit
+    grid = Grid(cells_per_unit * 3 // 2, cells_per_unit * 3 // 2, cells_per_unit * 2, h)
     centre = np.array([0.75, 0.75, 1.0])
     v, f = geodesic_sphere(freq)
     Xref_shell = centre + v * np.array([0.3, 0.3, 0.8])

@@ -1,0 +1,69 @@
+"""Shared helpers of the GPU parity tests: device transfer, oracle-side
+reference marshalling and the normwise error measures."""
+import numpy as np
+import torch
+
+import oracle as O
+from paper_1612_03399_amd import native as N
+
+DEV = "cuda"
+
+
+def dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_reference_from_oracle(ref, precision):
+    """The oracle's reference state in the library's layout (theta0 given by
+    its cosine and sine), rounded to the plan precision."""
+    dt = N.real_dtype(precision)
+    cs0 = np.stack([np.cos(ref.theta0), np.sin(ref.theta0)], axis=1)
+    return N.Reference(dev(ref.l0, dt), dev(cs0, dt), dev(ref.A0, dt), dev(ref.V0, torch.float64))
+
+
+def oracle_reference_as_seen(ref, precision):
+    """What the oracle must use to see the same (rounded) reference as the GPU."""
+    if precision == "f64":
+        return ref
+    f = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    th = np.arctan2(f(np.sin(ref.theta0)), f(np.cos(ref.theta0)))
+    return O.Reference(f(ref.l0), th, f(ref.A0), ref.V0.copy())
+
+
+def constants(wl):
+    return N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, DEV)
+
+
+def per_body_rel(y, yhat, node_off):
+    """max over bodies of ||y - yhat||_inf / ||yhat||_inf (rows = nodes)."""
+    worst = 0.0
+    for b in range(len(node_off) - 1):
+        s = slice(node_off[b], node_off[b + 1])
+        den = np.abs(yhat[s]).max()
+        if den == 0:
+            num = np.abs(y[s]).max()
+            worst = max(worst, num)
+            continue
+        worst = max(worst, np.abs(y[s] - yhat[s]).max() / den)
+    return worst
+
+
+def rel_inf(y, yhat):
+    den = np.abs(yhat).max()
+    return np.abs(y - yhat).max() / (den if den > 0 else 1.0)
+
+
+def elem_rel(y, yhat):
+    y, yhat = np.asarray(y), np.asarray(yhat)
+    den = np.maximum(np.abs(yhat), 1e-300)
+    return (np.abs(y - yhat) / den).max() if y.size else 0.0
+
+
+TOL = {"f64": 1e-12, "f32": 1e-5}

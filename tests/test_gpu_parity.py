@@ -1,0 +1,201 @@
+"""GPU parity: the HIP library (through its C-ABI) against the FP64 oracle,
+element by element on the same seeded inputs.  FP64 plans must agree to 1e-12
+relative (per-body normwise for node arrays, global normwise for grid fields,
+elementwise for per-body scalars), FP32 plans to 1e-5 against the oracle run
+on the same FP32-rounded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1612_03399_amd import native as N
+from paper_1612_03399_amd import workload as W
+
+from gpu_common import (DEV, TOL, constants, dev, elem_rel, gpu_reference_from_oracle, host,
+                        oracle_reference_as_seen, per_body_rel, rel_inf)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+CASES = {
+    "drop_L3_64": lambda: W.config0(),
+    "four_L2_32": lambda: W.small_suspension(4, 2, 32),
+    "uneven_small": lambda: W.config2(n_bodies=24, n=64),
+    "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
+                                         cells_per_unit=64),
+}
+
+
+def build(case, precision):
+    wl = CASES[case]()
+    ref = O.reference(wl)
+    return wl, ref
+
+
+def run_forces(wl, ref, precision):
+    plan = N.Plan(wl, wl.grid, precision)
+    gref = gpu_reference_from_oracle(ref, precision)
+    k = constants(wl)
+    X = dev(wl.X)
+    V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
+    A = torch.empty_like(V)
+    Wt = torch.empty(wl.n_bodies, 4, dtype=torch.float64, device=DEV)
+    F = N.ip_forces(plan, X, gref, k, V=V, A=A, W=Wt)
+    code, flags = N.ip_plan_status(plan)
+    return plan, host(F).astype(np.float64), host(V), host(A), host(Wt), code
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_forces_parity(case, precision):
+    say("forces", case, precision)
+    wl, ref = build(case, precision)
+    oref = oracle_reference_as_seen(ref, precision)
+    want = O.forces(wl, wl.X, oref)
+    plan, F, V, A, Wg, code = run_forces(wl, ref, precision)
+    assert code == N.IP_OK
+    tol = TOL[precision]
+    assert per_body_rel(F, want["F"], wl.node_off) <= tol
+    assert elem_rel(V[wl.closed == 1], want["V"][wl.closed == 1]) <= (1e-12 if precision == "f64" else 1e-7)
+    assert elem_rel(A, want["A"]) <= tol
+    assert elem_rel(Wg, want["W"]) <= (1e-10 if precision == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_reference_from(precision):
+    say("reference_from", precision)
+    wl = W.config3(freq=12, leaflet_quads=10, cells_per_unit=64)
+    ref = O.reference(wl)
+    plan = N.Plan(wl, wl.grid, precision)
+    g = N.ip_reference_from(plan, dev(wl.Xref))
+    torch.cuda.synchronize()
+    tol = 1e-14 if precision == "f64" else 1e-7
+    assert elem_rel(host(g.l0), ref.l0) <= tol
+    assert elem_rel(host(g.A0), ref.A0) <= tol
+    assert elem_rel(host(g.V0)[wl.closed == 1], ref.V0[wl.closed == 1]) <= 1e-14
+    cs = host(g.cs0).astype(np.float64)
+    assert np.abs(cs[:, 0] - np.cos(ref.theta0)).max() <= tol * 4
+    assert np.abs(cs[:, 1] - np.sin(ref.theta0)).max() <= tol * 4
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["drop_L3_64", "four_L2_32", "ventricle_small"])
+def test_interp_spread_parity(case, precision):
+    say("interp/spread", case, precision)
+    wl, ref = build(case, precision)
+    dt = N.real_dtype(precision)
+    u = wl.velocity()
+    if precision == "f32":
+        u = u.astype(np.float32).astype(np.float64)
+    plan = N.Plan(wl, wl.grid, precision)
+    X = dev(wl.X)
+    ud = dev(u, dt)
+    U = host(N.ibm_interp(plan, X, ud)).astype(np.float64)
+    want_U = O.interp(wl.X, wl.grid, u)
+    assert per_body_rel(U, want_U, wl.node_off) <= TOL[precision]
+    rng = np.random.default_rng(3)
+    Fn = rng.normal(size=wl.X.shape)
+    if precision == "f32":
+        Fn = Fn.astype(np.float32).astype(np.float64)
+    f = torch.zeros(3, wl.grid.nz, wl.grid.ny, wl.grid.nx, dtype=dt, device=DEV)
+    N.ibm_spread(plan, X, dev(Fn, dt), f)
+    want_f = O.spread(wl.X, Fn, wl.grid)
+    assert rel_inf(host(f).astype(np.float64), want_f) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_parity(case, precision):
+    say("step", case, precision)
+    wl, ref = build(case, precision)
+    dt_ = N.real_dtype(precision)
+    u = wl.velocity()
+    if precision == "f32":
+        u = u.astype(np.float32).astype(np.float64)
+    oref = oracle_reference_as_seen(ref, precision)
+    f_want = np.zeros_like(u)
+    want = O.step(wl, wl.X, oref, u, wl.dt, f_want)
+    plan = N.Plan(wl, wl.grid, precision)
+    X = dev(wl.X)
+    f = torch.zeros(u.shape, dtype=dt_, device=DEV)
+    V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
+    N.ip_step(plan, X, gpu_reference_from_oracle(ref, precision), constants(wl), dev(u, dt_), f,
+              wl.dt, V=V)
+    code, _ = N.ip_plan_status(plan)
+    assert code == N.IP_OK
+    # X_new = X + dX is rounded to the spacing of |X| on both sides, so the
+    # bar is the relative tolerance on dX plus two ulps of the positions
+    Xg, Xo = host(X), want["X"]
+    for b in range(wl.n_bodies):
+        s = slice(wl.node_off[b], wl.node_off[b + 1])
+        dx = np.abs(Xo[s] - wl.X[s]).max()
+        ulp = np.spacing(np.abs(wl.X[s]).max())
+        assert np.abs(Xg[s] - Xo[s]).max() <= TOL[precision] * dx + 2 * ulp
+    assert rel_inf(host(f).astype(np.float64), f_want) <= TOL[precision]
+    pin = wl.pinned == 1
+    if pin.any():
+        assert np.array_equal(host(X)[pin], wl.X[pin])
+
+
+def test_forces_deterministic():
+    say("determinism")
+    wl, ref = build("four_L2_32", "f64")
+    _, F1, *_ = run_forces(wl, ref, "f64")
+    _, F2, *_ = run_forces(wl, ref, "f64")
+    assert np.array_equal(F1, F2)
+
+
+def test_spread_adjoint_of_interp_on_gpu():
+    say("adjointness")
+    wl = W.small_suspension(4, 2, 32)
+    plan = N.Plan(wl, wl.grid, "f64")
+    rng = np.random.default_rng(0)
+    u = rng.normal(size=(3, 32, 32, 32))
+    Fn = rng.normal(size=wl.X.shape)
+    X = dev(wl.X)
+    U = host(N.ibm_interp(plan, X, dev(u)))
+    f = torch.zeros(u.shape, dtype=torch.float64, device=DEV)
+    N.ibm_spread(plan, X, dev(Fn), f)
+    lhs = (host(f) * u).sum() * wl.grid.h ** 3
+    rhs = (Fn * U).sum()
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(Fn * U).sum()
+
+
+def test_empty_batch_and_zero_force_reference():
+    say("edge cases")
+    wl = W.config0()
+    empty = W._assemble([], "empty", wl.grid, 1e-4, 1, "f64", (1.0, 1.0, 1.0, 1.0))
+    plan = N.Plan(empty, empty.grid, "f64")
+    z = torch.zeros(0, 3, dtype=torch.float64, device=DEV)
+    e = torch.zeros(0, dtype=torch.float64, device=DEV)
+    ref = N.Reference(e, torch.zeros(0, 2, dtype=torch.float64, device=DEV), e, e)
+    k = N.Constants(e, e, e, e, e)
+    F = N.ip_forces(plan, z, ref, k)
+    assert F.shape == (0, 3)
+    # at the reference configuration the forces vanish (GPU-computed reference)
+    plan = N.Plan(wl, wl.grid, "f64")
+    Xr = dev(wl.Xref)
+    g = N.ip_reference_from(plan, Xr)
+    F = host(N.ip_forces(plan, Xr, g, constants(wl)))
+    F_cur = host(N.ip_forces(plan, dev(wl.X), g, constants(wl)))
+    assert np.abs(F).max() <= 1e-13 * np.abs(F_cur).max()
+
+
+def test_degenerate_face_sets_status():
+    say("degenerate")
+    wl = W.config0()
+    ref = O.reference(wl)
+    X = wl.X.copy()
+    a, b, c = wl.faces[7]
+    X[c] = X[a]          # collapse one triangle (and the edges touching it)
+    plan = N.Plan(wl, wl.grid, "f64")
+    N.ip_forces(plan, dev(X), gpu_reference_from_oracle(ref, "f64"), constants(wl))
+    code, flags = N.ip_plan_status(plan)
+    assert code in (N.IP_ERR_DEGENERATE, N.IP_ERR_NONFINITE)
+    assert flags & N.IP_STATUS_DEGENERATE
+    code, flags = N.ip_plan_status(plan)      # cleared by the read
+    assert code == N.IP_OK and flags == 0
