@@ -62,7 +62,7 @@ void free_plan(ip_plan *p) {
     if (!p) return;
     void *ptrs[] = {p->node_off, p->edge_off, p->face_off, p->faces, p->edges4, p->closed,
                     p->pinned, p->csr_ptr, p->csr_slot, p->slots, p->Fbuf, p->Ubuf,
-                    p->Vbuf, p->Abuf, p->status};
+                    p->Vbuf, p->Abuf, p->status, p->fused_bodies};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -161,6 +161,33 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
     IP_TRY(upload(&p->Abuf, (const double *)nullptr, B));
     IP_TRY(upload(&p->status, (const uint32_t *)nullptr, 1));
     IP_HIP_CHECK(hipMemset(p->status, 0, sizeof(uint32_t)));
+
+    // fused step eligibility: every body fits one workgroup's registers and LDS
+    int max_n = 0;
+    for (int b = 0; b < B; ++b)
+        max_n = std::max(max_n, (int)(m->node_off[b + 1] - m->node_off[b]));
+    int lds_optin = 0;
+    IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin,
+                                       p->device));
+    if (lds_optin <= 0) IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin,
+                                     hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+    const int nmax = std::max(max_n, 1);
+    // LDS left for the grid tile once positions, accumulators and the cell list
+    // are placed (1 KB kept for the kernel's static shared memory)
+    const long long tile_bytes =
+        ((long long)lds_optin - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
+    p->fused_all = B > 0 && max_n <= kStepThreads * kStepNodesPerThread && tile_bytes >= 4096;
+    p->fused_tile_bytes = p->fused_all ? (int)std::min<long long>(tile_bytes, 1 << 20) : 0;
+    if (p->fused_all) {
+        std::vector<int32_t> order(B);
+        for (int b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return m->node_off[x + 1] - m->node_off[x] > m->node_off[y + 1] - m->node_off[y];
+        });
+        p->fused_nmax = nmax;
+        p->n_fused = B;
+        IP_TRY(upload(&p->fused_bodies, order.data(), B));
+    }
     IP_HIP_CHECK(hipDeviceSynchronize());
     return IP_OK;
 }
@@ -277,6 +304,7 @@ ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_co
         return arg_error("misaligned array");
     if (!(dt == dt)) return arg_error("dt is NaN");
     hipStream_t s = (hipStream_t)stream;
+    if (plan->fused_all) return launch_step_fused(plan, X, ref, k, u, f, dt, V, A, s);
     IP_TRY(launch_forces(plan, X, ref, k, plan->Fbuf, V, A, nullptr, s));
     IP_TRY(launch_interp(plan, X, u, plan->Ubuf, s));
     if (f) IP_TRY(launch_spread(plan, X, plan->Fbuf, f, s));

@@ -3,6 +3,7 @@
 // volume-gradient, and the scatter-free gather of element results into nodes.
 #include <cmath>
 
+#include "elements.h"
 #include "ipibm_internal.h"
 
 namespace {
@@ -32,11 +33,10 @@ __global__ __launch_bounds__(kGeomThreads) void k_geometry(
     double vs = 0.0, as = 0.0;
     for (int64_t f = face_off[b] + threadIdx.x; f < face_off[b + 1]; f += blockDim.x) {
         const int32_t *t = faces + 3 * f;
-        const vec3<double> xi = ldX(X, t[0]), xj = ldX(X, t[1]), xk = ldX(X, t[2]);
-        const vec3<double> ri = xi - a, rj = xj - a, rk = xk - a;
-        vs += dot(ri, cross(rj, rk));
-        const vec3<R> n = cross(diffR<R>(xj, xi), diffR<R>(xk, xi));
-        as += (double)sqrt(dot(n, n));
+        double v6, a2;
+        face_geometry<R>(ldX(X, t[0]), ldX(X, t[1]), ldX(X, t[2]), a, v6, a2);
+        vs += v6;
+        as += a2;
     }
     vs = block_sum(vs, sh);
     as = block_sum(as, sh);
@@ -84,23 +84,8 @@ __global__ void k_reference_faces(const double *__restrict__ X, const int32_t *_
 }
 
 // ----------------------------------------------------------------------------
-// Edge elements.  Spring W_e = 1/2 ks (l - l0)^2 on every edge and bending
-// hinge W_b = kb (1 - cos(theta - theta0)) where both wings exist.
-//
-// Hinge (v1, v2 | v3, v4), e = x2 - x1, nA = e x (x3 - x1), nB = (x4 - x1) x e,
-// |nA||nB| cos(theta) = nA.nB, |nA||nB| sin(theta) = (nA x nB).e / |e|.
-// dW/dtheta = kb sin(theta - theta0) = kb (sin c0 - cos s0).  The angle's
-// gradient: the wings move along their face normals,
-//   dtheta/dx3 = -|e| nA / |nA|^2,  dtheta/dx4 = -|e| nB / |nB|^2,
-// and the edge nodes take the unique combination that keeps theta invariant
-// under translation and rotation: with s3 = (x3-x1).e/|e|^2, s4 likewise,
-//   dtheta/dx1 = -(1-s3) dtheta/dx3 - (1-s4) dtheta/dx4,
-//   dtheta/dx2 = -s3 dtheta/dx3 - s4 dtheta/dx4.
-// The angle itself (normals, cos, sin, dW/dtheta) is always evaluated in FP64:
-// on fine smooth meshes theta - theta0 is ~1e-3 while FP32 edge vectors leave an
-// absolute error of ~1e-7 in sin(theta), which would cost FP32 plans four
-// digits of the bending force.  The force vectors are then formed in R.
-// Output: 4 slot vectors per edge (forces on v1..v4).
+// Edge elements (spring + bending hinge, see edge_forces): 4 slot vectors per
+// edge, the forces on v1..v4.
 // ----------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kElemThreads) void k_edges(
@@ -113,36 +98,15 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
     const int b = body_of(edge_off, B, e);
     const int4 q = e4[e];
     const vec3<double> x1 = ldX(X, q.x), x2 = ldX(X, q.y);
-    const vec3<R> ev = diffR<R>(x2, x1);
-    const R le2 = dot(ev, ev);
-    const R le = sqrt(le2);
-    const R fs = (R)ks[b] * (le - l0[e]) / le;
-    vec3<R> f1 = fs * ev;
-    vec3<R> f2 = (R)-1 * f1;
-    vec3<R> f3 = {0, 0, 0}, f4 = {0, 0, 0};
-    bool bad = !(le > (R)0);
-    if (q.z >= 0 && q.w >= 0) {
-        const vec3<double> x3 = ldX(X, q.z), x4 = ldX(X, q.w);
-        const vec3<double> evd = x2 - x1, d3d = x3 - x1, d4d = x4 - x1;
-        const vec3<double> nA = cross(evd, d3d);
-        const vec3<double> nB = cross(d4d, evd);
-        const double nA2 = dot(nA, nA), nB2 = dot(nB, nB);
-        bad |= !(nA2 > 0.0) || !(nB2 > 0.0);
-        const double led = sqrt(dot(evd, evd));
-        const double inv = 1.0 / sqrt(nA2 * nB2);
-        const double cth = dot(nA, nB) * inv;
-        const double sth = dot(cross(nA, nB), evd) * inv / led;
-        const double c0 = (double)cs0[2 * e], s0 = (double)cs0[2 * e + 1];
-        const double dW = kb[b] * (sth * c0 - cth * s0);
-        // F3 = -dW dtheta/dx3 = dW |e| nA/|nA|^2, F4 likewise
-        const R a3 = (R)(dW * led / nA2), a4 = (R)(dW * led / nB2);
-        f3 = a3 * vec3<R>{(R)nA.x, (R)nA.y, (R)nA.z};
-        f4 = a4 * vec3<R>{(R)nB.x, (R)nB.y, (R)nB.z};
-        const vec3<R> d3 = diffR<R>(x3, x1), d4 = diffR<R>(x4, x1);
-        const R s3 = dot(d3, ev) / le2, s4 = dot(d4, ev) / le2;
-        f1 = f1 - ((R)1 - s3) * f3 - ((R)1 - s4) * f4;
-        f2 = f2 - s3 * f3 - s4 * f4;
+    vec3<double> x3, x4;
+    const bool hinge = q.z >= 0 && q.w >= 0;
+    if (hinge) {
+        x3 = ldX(X, q.z);
+        x4 = ldX(X, q.w);
     }
+    vec3<R> f1, f2, f3, f4;
+    const bool bad = edge_forces<R>(x1, x2, hinge ? &x3 : nullptr, hinge ? &x4 : nullptr, l0[e],
+                                    cs0[2 * e], cs0[2 * e + 1], ks[b], kb[b], f1, f2, f3, f4);
     if (bad) atomicOr(status, IP_STATUS_DEGENERATE);
     R *o = slots + 12 * e;
     o[0] = f1.x; o[1] = f1.y; o[2] = f1.z;
@@ -152,47 +116,24 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
 }
 
 // ----------------------------------------------------------------------------
-// Face elements: area W_a = 1/2 kA (A - A0)^2 / A0 with dA/dx_i = 1/2 nhat x
-// (x_k - x_j) (cyclic), and, on closed bodies, the volume potential
-// W_v = 1/2 kV (V - V0)^2 / V0 (V from k_geometry).  Differentiating the
-// divergence-theorem volume gives dV/dx_i = (1/6) sum_{f ni i} (x_j - a) x (x_k - a)
-// for any anchor a; around the closed fan of node i the anchor terms cancel,
-// and taking a = x_i leaves dV/dx_i = (1/6) sum_{f ni i} n_f: every face hands
-// n_f / 6 to each of its corners.  This form has no anchor cancellation (the
-// anchored terms are ~|x - a| |edge| while their sum is ~|edge|^2).
-// Output: 3 slot vectors per face (forces on its corners).
+// Face elements (area + volume, see face_forces): 3 slot vectors per face, the
+// forces on its corners.  V from k_geometry.
 // ----------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(kElemThreads) void k_faces(
     const double *__restrict__ X, const int32_t *__restrict__ faces,
-    const int64_t *__restrict__ face_off, const int64_t *__restrict__ node_off, int B,
-    int64_t F, const R *__restrict__ A0, const double *__restrict__ V0,
-    const double *__restrict__ Vcur, const uint8_t *__restrict__ closed,
-    const double *__restrict__ kA, const double *__restrict__ kV, R *__restrict__ slots,
-    uint32_t *__restrict__ status) {
+    const int64_t *__restrict__ face_off, int B, int64_t F, const R *__restrict__ A0,
+    const double *__restrict__ V0, const double *__restrict__ Vcur,
+    const uint8_t *__restrict__ closed, const double *__restrict__ kA,
+    const double *__restrict__ kV, R *__restrict__ slots, uint32_t *__restrict__ status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const int b = body_of(face_off, B, f);
     const int32_t *t = faces + 3 * f;
-    const vec3<double> xi = ldX(X, t[0]), xj = ldX(X, t[1]), xk = ldX(X, t[2]);
-    const vec3<R> n = cross(diffR<R>(xj, xi), diffR<R>(xk, xi));
-    const R nn = sqrt(dot(n, n));
-    if (!(nn > (R)0)) atomicOr(status, IP_STATUS_DEGENERATE);
-    const R a0 = A0[f];
-    const R cA = (R)kA[b] * ((R)0.5 * nn - a0) / a0;   // dW_a/dA
-    // -cA * 1/2 nhat x edge  =  (-cA / (2|n|)) n x edge
-    const R sA = -cA / ((R)2 * nn);
-    vec3<R> gi = sA * cross(n, diffR<R>(xk, xj));
-    vec3<R> gj = sA * cross(n, diffR<R>(xi, xk));
-    vec3<R> gk = sA * cross(n, diffR<R>(xj, xi));
-    if (closed[b]) {
-        const double v0 = V0[b];
-        const R sV = (R)(-(double)kV[b] * (Vcur[b] - v0) / v0 * (1.0 / 6.0));
-        const vec3<R> gv = sV * n;
-        gi = gi + gv;
-        gj = gj + gv;
-        gk = gk + gv;
-    }
+    const R sV = volume_coefficient<R>(closed[b] != 0, kV[b], Vcur[b], V0[b]);
+    vec3<R> gi, gj, gk;
+    if (face_forces<R>(ldX(X, t[0]), ldX(X, t[1]), ldX(X, t[2]), A0[f], kA[b], sV, gi, gj, gk))
+        atomicOr(status, IP_STATUS_DEGENERATE);
     R *o = slots + 9 * f;
     o[0] = gi.x; o[1] = gi.y; o[2] = gi.z;
     o[3] = gj.x; o[4] = gj.y; o[5] = gj.z;
@@ -303,7 +244,7 @@ ip_status forces_impl(ip_plan *p, const double *X, const ip_reference *ref,
                            p->status);
     if (p->F > 0)
         hipLaunchKernelGGL(k_faces<R>, dim3(nblocks(p->F, kElemThreads)), dim3(kElemThreads), 0,
-                           s, X, p->faces, p->face_off, p->node_off, p->B, p->F,
+                           s, X, p->faces, p->face_off, p->B, p->F,
                            (const R *)ref->A0, ref->V0, Vb, p->closed, k->kA, k->kV,
                            slots + 12 * p->E, p->status);
     if (p->N > 0)

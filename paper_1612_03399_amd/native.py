@@ -15,7 +15,7 @@ import numpy as np
 import torch  # loads the HIP runtime the library binds to
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libipibm.so")
+LIB_PATH = os.environ.get("IPIBM_LIB", os.path.join(PKG, "libipibm.so"))
 
 IP_OK, IP_ERR_ARG, IP_ERR_HIP, IP_ERR_DEGENERATE, IP_ERR_NONFINITE, IP_ERR_OOM, \
     IP_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6

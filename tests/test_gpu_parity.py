@@ -21,8 +21,16 @@ def say(*a):
     print(*a, flush=True)
 
 
+def sparse_icosahedra():
+    """Level-0 icosahedra much larger than a cell: their bounding-box tile does
+    not fit the step kernel's LDS and the fused path falls back to direct
+    grid access."""
+    return W.suspension(n_bodies=3, level=0, r=0.2, n=48, sigma_rel=0.02, config=12, steps=1)
+
+
 CASES = {
     "drop_L3_64": lambda: W.config0(),
+    "sparse_L0_48": sparse_icosahedra,
     "four_L2_32": lambda: W.small_suspension(4, 2, 32),
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
