@@ -2,16 +2,19 @@
 
 A step is one pass of the whole forward hot path over the batch: the four
 interaction-potential families with the per-body volume and area reductions,
-the gather into nodes, interpolation of the staggered velocity, spreading of
-the nodal forces and the explicit update.  Workload: 1000 level-4 icosphere
-drops (2 562 000 nodes) on a 256^3 MAC grid, FP64, synthetic seeded inputs
-resident in HBM before the timed region.
+the accumulation into nodes, interpolation of the staggered velocity,
+spreading of the nodal forces and the explicit update.  The default workload
+is 1000 level-4 icosphere drops (2 562 000 nodes) on a 256^3 MAC grid in FP64,
+synthetic seeded inputs resident in HBM before the timed region.  With the
+fused path the step is one kernel launch (k_step_fused), so the events around
+the timed steps measure that kernel on the stream it is launched on.
 
-Prints ONE JSON line (see the metric contract in the design notes).
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+KERNEL_SOURCES = ["paper_1612_03399_amd/csrc/k_step.hip", "paper_1612_03399_amd/csrc/elements.h",
+                  "paper_1612_03399_amd/csrc/ipibm_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fused_{workload}_{dtype}.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def touched_points(X, grid):
@@ -45,21 +59,35 @@ def touched_points(X, grid):
 
 
 def algorithmic_bytes(wl, touched, real_bytes):
-    """Bytes one fused step must move at minimum: X read + write, the
-    connectivity and reference arrays as the API holds them, the pinned mask,
-    per-body arrays, u read and f read-modify-write over the touched set."""
+    """Bytes one step must move at minimum, in the layout the library takes:
+    X read + write (FP64), pinned mask, connectivity (int32), reference arrays
+    l0, (cos, sin) theta0, A0 (real), per-body arrays, u read and f
+    read-modify-write over the touched grid points."""
     N, E, F, B = wl.n_nodes, wl.n_edges, wl.n_faces, wl.n_bodies
-    nodes = N * (8 * 3 * 2 + 1)                      # X r+w (FP64), pinned
-    edges = E * (16 + real_bytes * 3)                # edges4, l0, cs0[2]
-    faces = F * (12 + real_bytes)                    # faces, A0
-    bodies = B * 8 * (5 + 1 + 2) + B * (1 + 8 * 3)   # k's+mass, V0, V/A out, closed, offsets
-    grid = touched * real_bytes * 3                  # u read, f read + write
+    nodes = N * (8 * 3 * 2 + 1)
+    edges = E * (16 + real_bytes * 3)
+    faces = F * (12 + real_bytes)
+    bodies = B * (8 * 8 + 1 + 8 * 3)      # ks kb kA kV mass V0 V A, closed, offsets
+    grid = touched * real_bytes * 3       # u read, f read + write
     return nodes + edges + faces + bodies + grid
+
+
+def load_traffic(workload, dtype, nbytes_launch):
+    """Measured HBM bytes per launch from the committed counter summary, when it
+    was taken on the current kernel sources (else None)."""
+    path = TRAFFIC_FILE.format(workload=workload, dtype=dtype)
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash():
+        return None, "stale (kernel changed since the counters were taken)"
+    return t["bytes_per_launch"], path
 
 
 def cpu_baseline(wl, u, budget_s=20.0):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the
-    same workload: whole-batch steps until ~budget_s of CPU work."""
+    same workload: whole-batch steps until ~budget_s/2 of CPU work."""
     import oracle as O
     ref = O.reference(wl)
     f = np.zeros_like(u)
@@ -78,6 +106,20 @@ def cpu_baseline(wl, u, budget_s=20.0):
                       f"({wl.n_nodes} nodes), {el:.1f} s"}
 
 
+def time_steps(N, plan, X, ref, k, u, f, dt, V, A, steps, warmup, stream, torch):
+    for _ in range(warmup):
+        N.ip_step(plan, X, ref, k, u, f, dt, V, A, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        N.ip_step(plan, X, ref, k, u, f, dt, V, A, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +128,9 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--bodies", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and graph legs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -100,44 +145,44 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 512 MiB read + 512 MiB written")
+
     wl = W.config1(n_bodies=args.bodies, precision=args.precision)
     log(f"workload {wl.name}: {wl.n_nodes} nodes, {wl.n_edges} edges, {wl.n_faces} faces")
     u_host = wl.velocity(dtype=np.float64)
-    rdt = N.real_dtype(args.precision)
-    u = torch.as_tensor(u_host).to(dev, rdt)
-    plan = N.Plan(wl, wl.grid, args.precision)
-    ref = N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev))
-    k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
-    X = torch.as_tensor(wl.X).to(dev)
-    f = torch.zeros(u.shape, dtype=rdt, device=dev)
-    V = torch.empty(wl.n_bodies, dtype=torch.float64, device=dev)
-    A = torch.empty_like(V)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        N.ip_step(plan, X, ref, k, u, f, wl.dt, V, A, stream)
-    torch.cuda.synchronize()
+    def setup(precision):
+        rdt = N.real_dtype(precision)
+        u = torch.as_tensor(u_host).to(dev, rdt)
+        plan = N.Plan(wl, wl.grid, precision)
+        ref = N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev))
+        k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
+        X = torch.as_tensor(wl.X).to(dev)
+        f = torch.zeros(u.shape, dtype=rdt, device=dev)
+        V = torch.empty(wl.n_bodies, dtype=torch.float64, device=dev)
+        A = torch.empty_like(V)
+        return plan, ref, k, X, u, f, V, A
+
+    plan, ref, k, X, u, f, V, A = setup(args.precision)
+    ms = time_steps(N, plan, X, ref, k, u, f, wl.dt, V, A, args.steps, args.warmup, stream, torch)
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags}")
-    log(f"warmup done ({args.warmup} steps)")
-
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        N.ip_step(plan, X, ref, k, u, f, wl.dt, V, A, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    log(f"timed {args.steps} steps: {ms:.4f} ms/step")
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (fused path: {plan.fused})")
 
     real_bytes = 8 if args.precision == "f64" else 4
     touched = touched_points(wl.X, wl.grid)
     bytes_step = algorithmic_bytes(wl, touched, real_bytes)
     gbs = bytes_step / (ms * 1e-3) / 1e9
     value = wl.n_nodes / (ms * 1e-3)
+    traffic, traffic_src = load_traffic(wl.name, args.precision, bytes_step)
 
     out = {
         "metric": "Lagrangian node-steps/s (forces+interp+spread+update)",
@@ -149,10 +194,52 @@ def main():
                    "edges": wl.n_edges, "faces": wl.n_faces,
                    "grid": [wl.grid.nx, wl.grid.ny, wl.grid.nz], "dt": wl.dt},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "whole step", "bytes_per_step": bytes_step,
-                     "bytes_per_node": bytes_step / wl.n_nodes, "touched_grid_points": touched},
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step_fused" if plan.fused else "unfused step",
+                     "algorithmic_bytes_per_launch": bytes_step,
+                     "bytes_per_node": bytes_step / wl.n_nodes,
+                     "touched_grid_points": touched,
+                     "traffic_source": traffic_src},
     }
+    del plan, ref, k, X, u, f
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        extras = {}
+        other = "f32" if args.precision == "f64" else "f64"
+        plan2, ref2, k2, X2, u2, f2, V2, A2 = setup(other)
+        ms2 = time_steps(N, plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, args.steps,
+                         args.warmup, stream, torch)
+        extras[f"{other}_ms_per_step"] = ms2
+        extras[f"{other}_node_steps_per_s"] = wl.n_nodes / (ms2 * 1e-3)
+        log(f"{other}: {ms2:.4f} ms/step")
+        # the same steps captured once in a hipGraph and replayed
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            N.ip_step(plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            for _ in range(10):
+                N.ip_step(plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2,
+                          torch.cuda.current_stream())
+        g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(1, args.steps // 10)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        extras[f"{other}_graph_ms_per_step"] = e0.elapsed_time(e1) / (10 * reps)
+        log(f"{other} graph replay: {extras[f'{other}_graph_ms_per_step']:.4f} ms/step")
+        out["extras"] = extras
+        del g, plan2
+
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, u_host)

@@ -126,6 +126,13 @@ ip_status ip_plan_destroy(ip_plan *plan);
 /* Sizes: counts[0..3] = bodies, nodes, edges, faces. */
 ip_status ip_plan_sizes(const ip_plan *plan, int64_t counts[4]);
 
+/* Execution properties chosen at plan time: props[0] = 1 if ip_step runs the
+ * fused one-workgroup-per-body kernel (every body fits its LDS layout), else 0
+ * (separate element, gather, transfer and update kernels); props[1] = nodes of
+ * the largest body; props[2] = LDS bytes of the per-body grid tile;
+ * props[3] = threads per workgroup of the fused kernel. */
+ip_status ip_plan_properties(const ip_plan *plan, int64_t props[4]);
+
 /* Reference state from reference positions Xref[N][3] (Section 2.3 "initial
  * (reference) state").  Writes l0[E], cs0[E][2], A0[F] (real) and V0[B]
  * (double).  The signed angle follows the forces' convention: positive for a

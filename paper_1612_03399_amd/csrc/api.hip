@@ -187,6 +187,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
         p->fused_nmax = nmax;
         p->n_fused = B;
         IP_TRY(upload(&p->fused_bodies, order.data(), B));
+        IP_TRY(prepare_step_fused(p));
     }
     IP_HIP_CHECK(hipDeviceSynchronize());
     return IP_OK;
@@ -251,6 +252,15 @@ ip_status ip_plan_sizes(const ip_plan *plan, int64_t counts[4]) {
     counts[1] = plan->N;
     counts[2] = plan->E;
     counts[3] = plan->F;
+    return IP_OK;
+}
+
+ip_status ip_plan_properties(const ip_plan *plan, int64_t props[4]) {
+    if (!plan || !props) return arg_error("NULL argument");
+    props[0] = plan->fused_all ? 1 : 0;
+    props[1] = plan->fused_nmax;
+    props[2] = plan->fused_tile_bytes;
+    props[3] = kStepThreads;
     return IP_OK;
 }
 

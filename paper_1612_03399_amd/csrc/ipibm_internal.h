@@ -83,6 +83,7 @@ ip_status launch_update(ip_plan *p, double *X, const void *U, const void *F,
 constexpr int kStepThreads = 1024;
 constexpr int kStepNodesPerThread = 3;
 size_t step_fused_lds_bytes(int nmax, int tile_bytes);
+ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
 ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
                             const ip_constants *k, const void *u, void *f, double dt,
                             double *V, double *A, hipStream_t s);

@@ -360,22 +360,31 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
         const R *cs0 = (const R *)a.cs0 + 2 * e0;
         const int4 *eb = a.e4 + e0;
         const double ks = a.ks[b], kb = a.kb[b];
-        int4 nq = {0, 0, -1, -1};
-        R nl0 = (R)1, nc0 = (R)1, ns0 = (R)0;
-        if (tid < E) {
-            nq = eb[tid];
-            nl0 = l0[tid];
-            nc0 = cs0[2 * tid];
-            ns0 = cs0[2 * tid + 1];
+        // edge data two iterations ahead: slot 0 = next, slot 1 = the one after
+        int4 nq[2] = {{0, 0, -1, -1}, {0, 0, -1, -1}};
+        R nl0[2] = {(R)1, (R)1}, nc0[2] = {(R)1, (R)1}, ns0[2] = {(R)0, (R)0};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int t = tid + k * NT;
+            if (t < E) {
+                nq[k] = eb[t];
+                nl0[k] = l0[t];
+                nc0[k] = cs0[2 * t];
+                ns0[k] = cs0[2 * t + 1];
+            }
         }
         for (int t = tid; t < E; t += NT) {
-            const int4 q = nq;
-            const R el0 = nl0, c0 = nc0, s0 = ns0;
-            if (t + NT < E) {      // next edge's data in flight during this one
-                nq = eb[t + NT];
-                nl0 = l0[t + NT];
-                nc0 = cs0[2 * (t + NT)];
-                ns0 = cs0[2 * (t + NT) + 1];
+            const int4 q = nq[0];
+            const R el0 = nl0[0], c0 = nc0[0], s0 = ns0[0];
+            nq[0] = nq[1];
+            nl0[0] = nl0[1];
+            nc0[0] = nc0[1];
+            ns0[0] = ns0[1];
+            if (t + 2 * NT < E) {
+                nq[1] = eb[t + 2 * NT];
+                nl0[1] = l0[t + 2 * NT];
+                nc0[1] = cs0[2 * (t + 2 * NT)];
+                ns0[1] = cs0[2 * (t + 2 * NT) + 1];
             }
             const int i1 = q.x - (int)n0, i2 = q.y - (int)n0;
             const bool hinge = q.z >= 0 && q.w >= 0;
@@ -542,6 +551,13 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
 
     // ---- P5: interpolation and update, one lattice (= one component) at a time ----
     const double cm = a.dt * a.dt / a.mass[b];
+    bool pinned[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int j = tid + s * NT;
+        pinned[s] = j < N && a.pinned[n0 + j];
+    }
+    __syncthreads();      // every thread is done reading xs (spreading)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const R *ud = (const R *)a.u + d * a.field;
@@ -585,11 +601,14 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
             }
             const double fd = Fs[3 * pos[s] + d];
             if (!isfinite(fd) || !isfinite((double)acc)) atomicOr(a.status, IP_STATUS_NONFINITE);
-            if (!a.pinned[n0 + j])
-                a.X[3 * (n0 + j) + d] = xr[s][d] + a.dt * (double)acc + cm * (double)(R)fd;
+            // new position staged in xs (free once spreading is done), in the
+            // original node order, and written to memory once below
+            xs[3 * j + d] = pinned[s] ? xr[s][d] : xr[s][d] + a.dt * (double)acc + cm * (double)(R)fd;
         }
         if (use_tile) __syncthreads();
     }
+    __syncthreads();
+    for (int i = tid; i < 3 * N; i += NT) a.X[3 * n0 + i] = xs[i];
     if (bad) atomicOr(a.status, IP_STATUS_DEGENERATE);
 }
 
@@ -598,6 +617,17 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
 size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
     // xs + Fs (FP64), the tile region, the occupied-cell list (start, count)
     return (size_t)nmax * 48 + (size_t)tile_bytes + (size_t)nmax * 2 * sizeof(uint16_t);
+}
+
+ip_status prepare_step_fused(ip_plan *p) {
+    const int lds = (int)step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
+    if (p->prec == IP_F64)
+        IP_HIP_CHECK(hipFuncSetAttribute((const void *)k_step_fused<double>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    else
+        IP_HIP_CHECK(hipFuncSetAttribute((const void *)k_step_fused<float>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    return IP_OK;
 }
 
 ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
@@ -639,15 +669,10 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
     a.nmax = p->fused_nmax;
     a.tile_bytes = p->fused_tile_bytes;
     const size_t lds = step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    if (p->prec == IP_F64) {
-        IP_HIP_CHECK(hipFuncSetAttribute((const void *)k_step_fused<double>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_step_fused<double>, dim3(p->n_fused), dim3(NT), lds, s, a);
-    } else {
-        IP_HIP_CHECK(hipFuncSetAttribute((const void *)k_step_fused<float>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    else
         hipLaunchKernelGGL(k_step_fused<float>, dim3(p->n_fused), dim3(NT), lds, s, a);
-    }
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }

@@ -60,6 +60,7 @@ def _load():
         "ip_plan_create": [C.POINTER(vp), C.POINTER(ip_mesh), C.POINTER(ip_grid), i32],
         "ip_plan_destroy": [vp],
         "ip_plan_sizes": [vp, C.POINTER(C.c_int64)],
+        "ip_plan_properties": [vp, C.POINTER(C.c_int64)],
         "ip_reference_from": [vp, vp, vp, vp, vp, vp, vp],
         "ip_forces": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp, vp, vp,
                       vp],
@@ -172,6 +173,10 @@ class Plan:
         counts = (C.c_int64 * 4)()
         _check(LIB.ip_plan_sizes(h, counts))
         self.B, self.N, self.E, self.F = (int(c) for c in counts)
+        props = (C.c_int64 * 4)()
+        _check(LIB.ip_plan_properties(h, props))
+        self.fused = bool(props[0])
+        self.largest_body, self.tile_bytes, self.step_threads = (int(v) for v in props[1:])
 
     def close(self):
         if getattr(self, "handle", None):
