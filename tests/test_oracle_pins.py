@@ -458,3 +458,24 @@ def test_rollout_gradient_fd():
     fd = (loss(uu=u + eps * w) - loss(uu=u - eps * w)) / (2 * eps)
     an = (out["gu"] * w).sum()
     assert abs(fd - an) <= 1e-6 * abs(an) + 1e-10, (fd, an)
+
+
+def test_rollout_gradient_at_zero_constant():
+    """dL/dk_s is defined where k_s = 0 (each family is linear in its own
+    constant): a central difference around k_b = 0 pins it (step 1e-4: the
+    loss is curved in k_b on the 1e-2 scale of the nominal bending constant)."""
+    wl, ref, u = small_calibration_case()
+    dt, steps = 2e-2, 2
+    Ds = np.array([0.05])
+    k0 = np.array([[1.0], [0.0], [0.1], [1.0]])
+    out = O.rollout_grad(wl, wl.X, ref, u, dt, steps, Ds, k0)
+    d = 1e-4
+    kp, km = k0.copy(), k0.copy()
+    kp[1] += d
+    km[1] -= d
+    lp = O.rollout_grad(wl, wl.X, ref, u, dt, steps, Ds, kp)["loss"]
+    lm = O.rollout_grad(wl, wl.X, ref, u, dt, steps, Ds, km)["loss"]
+    fd = (lp - lm) / (2 * d)
+    an = out["gk"][1, 0]
+    assert an != 0.0
+    assert abs(fd - an) <= 1e-5 * abs(an) + 1e-11, (fd, an)
