@@ -120,6 +120,46 @@ def time_steps(N, plan, X, ref, k, u, f, dt, V, A, steps, warmup, stream, torch)
     return e0.elapsed_time(e1) / steps
 
 
+def backward_leg(N, W, bodies, dev, torch, log, steps=10, reps=3):
+    """Differentiation workload: the same suspension, loss = sum_b (D_b - D*_b)^2
+    on the Taylor deformation after 10 steps, D* ~ U[0.05, 0.2]; gradients with
+    respect to X0, u and the per-body constants by the reverse pass over
+    checkpoints.  Times the forward (steps + checkpoint copies + loss) and the
+    backward separately."""
+    from paper_1612_03399_amd import autograd as AG
+    wl = W.config4(n_bodies=bodies)
+    u = torch.as_tensor(wl.velocity(dtype=np.float64)).to(dev)
+    plan = N.Plan(wl, wl.grid, "f64")
+    ref = N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev))
+    km = torch.as_tensor(np.stack([wl.ks, wl.kb, wl.kA, wl.kV])).to(dev)
+    mass = torch.as_tensor(np.asarray(wl.mass, np.float64)).to(dev)
+    Ds = torch.as_tensor(wl.targets).to(dev)
+    X0 = torch.as_tensor(wl.X).to(dev)
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        x0 = X0.clone().requires_grad_(True)
+        uu = u.clone().requires_grad_(True)
+        kk = km.clone().requires_grad_(True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record()
+        loss = AG.taylor_loss(plan, AG.rollout(plan, x0, uu, kk, ref, mass, wl.dt, steps), Ds)
+        e[1].record()
+        loss.backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        if r > 0:                       # the first pass allocates the workspace
+            fwd.append(e[0].elapsed_time(e[1]))
+            bwd.append(e[1].elapsed_time(e[2]))
+    f, b = float(np.median(fwd)), float(np.median(bwd))
+    log(f"backward leg: fwd {f:.3f} ms, bwd {b:.3f} ms for {steps} steps (ratio {b / f:.2f})")
+    code, flags = N.ip_plan_status(plan)
+    if code != N.IP_OK:
+        raise SystemExit(f"device status {code} flags {flags} in the backward leg")
+    return {"diff_workload": wl.name, "diff_steps": steps, "diff_fwd_ms": f, "diff_bwd_ms": b,
+            "diff_bwd_over_fwd": b / f, "diff_loss": float(loss.item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +279,9 @@ def main():
         log(f"{other} graph replay: {extras[f'{other}_graph_ms_per_step']:.4f} ms/step")
         out["extras"] = extras
         del g, plan2
+
+    if not args.no_extras and args.precision == "f64":
+        out.setdefault("extras", {}).update(backward_leg(N, W, args.bodies, dev, torch, log))
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

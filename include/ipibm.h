@@ -177,6 +177,41 @@ ip_status ibm_spread(ip_plan *plan, const double *X, const void *F, void *f, voi
 ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_constants *k,
                   const void *u, void *f, double dt, double *V, double *A, void *stream);
 
+/* ---- derivatives (IP_F64 plans; IP_ERR_UNSUPPORTED otherwise) ---- */
+
+/* Directional derivative of the forces: dF = (dF/dX) dX, where F is the force
+ * of ip_forces.  F = -grad W, so dF/dX is the negated Hessian of the total
+ * potential: symmetric, and this product is also the vector-Jacobian product.
+ * Evaluated in forward mode (dual numbers) through the element code, with the
+ * volume term's rank-one part from the tangent of each body's volume.
+ * X, dX, dF: double[N][3] (dF overwritten).  Deterministic (gather lists). */
+ip_status ip_forces_jvp(ip_plan *plan, const double *X, const double *dX,
+                        const ip_reference *ref, const ip_constants *k, double *dF,
+                        void *stream);
+
+/* Reverse mode of one ip_step.  With the update X' = X + M (dt U(X) + dt^2/m
+ * F(X; k)), M = not-pinned mask, and the adjoint lam_next = dL/dX', writes
+ *   lam = lam_next + dt J_U(X)^T P + (dt^2/m) (dF/dX) P,   P = M lam_next,
+ * and ACCUMULATES
+ *   gk[s][b] += (dt^2/m_b) sum_{l in b} (F_s,l / k_s) . P_l   (s = spring,
+ *               bending, area, volume; gk is double[4][B], may be NULL)
+ *   gu       += dt h^3 spread(P)   (double[3][nz][ny][nx], may be NULL; the
+ *               adjoint of interpolation is spreading).
+ * X is the position at which the forward step was taken (a checkpoint).
+ * lam may alias lam_next.  The first call allocates a workspace of
+ * 16 (E + F) bytes; later calls allocate nothing. */
+ip_status ip_step_vjp(ip_plan *plan, const double *X, const ip_reference *ref,
+                      const ip_constants *k, const double *u, double dt, const double *lam_next,
+                      double *lam, double *gk, double *gu, void *stream);
+
+/* Taylor deformation of every body (Section 3.1 measure D = (L - B)/(L + B)):
+ * L^2 and B^2 are the largest and smallest eigenvalues of the node covariance
+ * C = (1/n) sum (x - c)(x - c)^T (our reading of the semi-axes).  D[B] may be
+ * NULL.  With Dstar[B] given, also loss[b] = (D_b - Dstar_b)^2 and the
+ * gradient gX[N][3] of sum_b loss[b] (overwritten).  All device double. */
+ip_status ip_taylor(ip_plan *plan, const double *X, const double *Dstar, double *D,
+                    double *loss, double *gX, void *stream);
+
 /* Wait for the plan's work on `stream`, read and clear the status word.
  * Returns IP_OK, IP_ERR_DEGENERATE or IP_ERR_NONFINITE; *flags (may be NULL)
  * receives the raw bits. */

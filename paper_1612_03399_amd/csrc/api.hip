@@ -62,7 +62,7 @@ void free_plan(ip_plan *p) {
     if (!p) return;
     void *ptrs[] = {p->node_off, p->edge_off, p->face_off, p->faces, p->edges4, p->closed,
                     p->pinned, p->csr_ptr, p->csr_slot, p->slots, p->Fbuf, p->Ubuf,
-                    p->Vbuf, p->Abuf, p->status, p->fused_bodies};
+                    p->Vbuf, p->Abuf, p->status, p->fused_bodies, p->bwd_dots};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -319,6 +319,46 @@ ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_co
     IP_TRY(launch_interp(plan, X, u, plan->Ubuf, s));
     if (f) IP_TRY(launch_spread(plan, X, plan->Fbuf, f, s));
     return launch_update(plan, X, plan->Ubuf, plan->Fbuf, k, dt, s);
+}
+
+ip_status ip_forces_jvp(ip_plan *plan, const double *X, const double *dX,
+                        const ip_reference *ref, const ip_constants *k, double *dF,
+                        void *stream) {
+    IP_TRY(check_plan(plan));
+    if (plan->prec != IP_F64)
+        return (ipibm_set_error("derivatives need an IP_F64 plan"), IP_ERR_UNSUPPORTED);
+    IP_TRY(check_ref_k(plan, ref, k, false));
+    if (plan->N > 0 && (!X || !dX || !dF)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(dX, 8) || !aligned(dF, 8)) return arg_error("misaligned array");
+    return launch_forces_jvp(plan, X, dX, ref, k, nullptr, dF, nullptr, nullptr,
+                             (hipStream_t)stream);
+}
+
+ip_status ip_step_vjp(ip_plan *plan, const double *X, const ip_reference *ref,
+                      const ip_constants *k, const double *u, double dt, const double *lam_next,
+                      double *lam, double *gk, double *gu, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (plan->prec != IP_F64)
+        return (ipibm_set_error("derivatives need an IP_F64 plan"), IP_ERR_UNSUPPORTED);
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    IP_TRY(check_ref_k(plan, ref, k, true));
+    if (plan->N > 0 && (!X || !u || !lam_next || !lam)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(u, 8) || !aligned(lam_next, 8) || !aligned(lam, 8) ||
+        !aligned(gk, 8) || !aligned(gu, 8))
+        return arg_error("misaligned array");
+    if (!plan->bwd_dots && plan->E + plan->F > 0)
+        IP_TRY(alloc_bytes((void **)&plan->bwd_dots, (size_t)(plan->E + plan->F) * 2 * sizeof(double)));
+    return launch_step_vjp(plan, X, ref, k, (const double *)u, dt, lam_next, lam, gk,
+                           (double *)gu, (hipStream_t)stream);
+}
+
+ip_status ip_taylor(ip_plan *plan, const double *X, const double *Dstar, double *D,
+                    double *loss, double *gX, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (plan->N > 0 && !X) return arg_error("X is NULL");
+    if (Dstar && (!loss || !gX)) return arg_error("loss and gX are required with Dstar");
+    if (!aligned(X, 8)) return arg_error("misaligned X");
+    return launch_taylor(plan, X, Dstar, D, loss, gX, (hipStream_t)stream);
 }
 
 ip_status ip_plan_status(ip_plan *plan, void *stream, uint32_t *flags) {

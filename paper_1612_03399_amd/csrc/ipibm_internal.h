@@ -64,6 +64,8 @@ struct ip_plan {
     int fused_tile_bytes = 0;     // LDS bytes for the per-body grid tile
     int32_t *fused_bodies = nullptr;  // [n_fused] body ids, largest first
 
+    double *bwd_dots = nullptr;   // [2E + 2F] family dot products (reverse step)
+
     size_t real_size() const { return prec == IP_F64 ? sizeof(double) : sizeof(float); }
 };
 
@@ -78,6 +80,17 @@ ip_status launch_interp(ip_plan *p, const double *X, const void *u, void *U, hip
 ip_status launch_spread(ip_plan *p, const double *X, const void *F, void *f, hipStream_t s);
 ip_status launch_update(ip_plan *p, double *X, const void *U, const void *F,
                         const ip_constants *k, double dt, hipStream_t s);
+
+// derivatives (k_backward.hip), FP64 plans
+ip_status launch_forces_jvp(ip_plan *p, const double *X, const double *T, const ip_reference *ref,
+                            const ip_constants *k, const double *P, double *dF, double *dotE,
+                            double *dotF, hipStream_t s);
+ip_status launch_step_vjp(ip_plan *p, const double *X, const ip_reference *ref,
+                          const ip_constants *k, const double *u, double dt,
+                          const double *lam_in, double *lam_out, double *gk, double *gu,
+                          hipStream_t s);
+ip_status launch_taylor(ip_plan *p, const double *X, const double *Dstar, double *D, double *loss,
+                        double *gX, hipStream_t s);
 
 // fused step (k_step.hip)
 constexpr int kStepThreads = 1024;

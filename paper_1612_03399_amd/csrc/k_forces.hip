@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_geometry(
     for (int64_t f = face_off[b] + threadIdx.x; f < face_off[b + 1]; f += blockDim.x) {
         const int32_t *t = faces + 3 * f;
         double v6, a2;
-        face_geometry<R>(ldX(X, t[0]), ldX(X, t[1]), ldX(X, t[2]), a, v6, a2);
+        face_geometry<double, R>(ldX(X, t[0]), ldX(X, t[1]), ldX(X, t[2]), a, v6, a2);
         vs += v6;
         as += a2;
     }
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
         x4 = ldX(X, q.w);
     }
     vec3<R> f1, f2, f3, f4;
-    const bool bad = edge_forces<R>(x1, x2, hinge ? &x3 : nullptr, hinge ? &x4 : nullptr, l0[e],
+    const bool bad = edge_forces<double, R>(x1, x2, hinge ? &x3 : nullptr, hinge ? &x4 : nullptr, l0[e],
                                     cs0[2 * e], cs0[2 * e + 1], ks[b], kb[b], f1, f2, f3, f4);
     if (bad) atomicOr(status, IP_STATUS_DEGENERATE);
     R *o = slots + 12 * e;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kElemThreads) void k_faces(
     const int32_t *t = faces + 3 * f;
     const R sV = volume_coefficient<R>(closed[b] != 0, kV[b], Vcur[b], V0[b]);
     vec3<R> gi, gj, gk;
-    if (face_forces<R>(ldX(X, t[0]), ldX(X, t[1]), ldX(X, t[2]), A0[f], kA[b], sV, gi, gj, gk))
+    if (face_forces<double, R>(ldX(X, t[0]), ldX(X, t[1]), ldX(X, t[2]), A0[f], kA[b], sV, gi, gj, gk))
         atomicOr(status, IP_STATUS_DEGENERATE);
     R *o = slots + 9 * f;
     o[0] = gi.x; o[1] = gi.y; o[2] = gi.z;

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     for (int t = tid; t < F; t += NT) {
         const int32_t *tr = a.faces + 3 * (f0 + t);
         double v, ar;
-        face_geometry<R>(ldx(xs, tr[0] - (int)n0), ldx(xs, tr[1] - (int)n0),
+        face_geometry<double, R>(ldx(xs, tr[0] - (int)n0), ldx(xs, tr[1] - (int)n0),
                          ldx(xs, tr[2] - (int)n0), anchor, v, ar);
         v6 += v;
         a2 += ar;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
                 na0 = A0[t + NT];
             }
             vec3<R> gi, gj, gk;
-            bad |= face_forces<R>(ldx(xs, i), ldx(xs, j), ldx(xs, k), a0, kA, sV, gi, gj, gk);
+            bad |= face_forces<double, R>(ldx(xs, i), ldx(xs, j), ldx(xs, k), a0, kA, sV, gi, gj, gk);
             add3(Fs, i, gi);
             add3(Fs, j, gj);
             add3(Fs, k, gk);
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
             const int i3 = hinge ? q.z - (int)n0 : 0, i4 = hinge ? q.w - (int)n0 : 0;
             const vec3<double> x3 = ldx(xs, i3), x4 = ldx(xs, i4);
             vec3<R> f1, f2, f3, f4;
-            bad |= edge_forces<R>(ldx(xs, i1), ldx(xs, i2), hinge ? &x3 : nullptr,
+            bad |= edge_forces<double, R>(ldx(xs, i1), ldx(xs, i2), hinge ? &x3 : nullptr,
                                   hinge ? &x4 : nullptr, el0, c0, s0, ks, kb, f1, f2, f3, f4);
             add3(Fs, i1, f1);
             add3(Fs, i2, f2);

@@ -69,6 +69,10 @@ def _load():
         "ip_step": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp, d, vp,
                     vp, vp],
         "ip_plan_status": [vp, vp, C.POINTER(C.c_uint32)],
+        "ip_forces_jvp": [vp, vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp],
+        "ip_step_vjp": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, d, vp, vp,
+                        vp, vp, vp],
+        "ip_taylor": [vp, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -241,3 +245,35 @@ def ip_plan_status(plan: Plan, stream=None):
     if code not in (IP_OK, IP_ERR_DEGENERATE, IP_ERR_NONFINITE):
         _check(code)
     return code, int(flags.value)
+
+
+def ip_forces_jvp(plan: Plan, X, dX, ref: Reference, k: Constants, dF=None, stream=None):
+    if dF is None:
+        dF = torch.empty_like(X)
+    r, kk = ref.struct(), k.struct()
+    _check(LIB.ip_forces_jvp(plan.handle, _ptr(X), _ptr(dX), C.byref(r), C.byref(kk), _ptr(dF),
+                             _stream(stream)))
+    return dF
+
+
+def ip_step_vjp(plan: Plan, X, ref: Reference, k: Constants, u, dt, lam_next, lam=None,
+                gk=None, gu=None, stream=None):
+    if lam is None:
+        lam = torch.empty_like(lam_next)
+    r, kk = ref.struct(), k.struct()
+    _check(LIB.ip_step_vjp(plan.handle, _ptr(X), C.byref(r), C.byref(kk), _ptr(u), float(dt),
+                           _ptr(lam_next), _ptr(lam), _ptr(gk), _ptr(gu), _stream(stream)))
+    return lam
+
+
+def ip_taylor(plan: Plan, X, Dstar=None, stream=None):
+    """Returns D[B], or (D, loss[B], gX[N,3]) when Dstar is given."""
+    D = torch.empty(plan.B, dtype=torch.float64, device=X.device)
+    if Dstar is None:
+        _check(LIB.ip_taylor(plan.handle, _ptr(X), None, _ptr(D), None, None, _stream(stream)))
+        return D
+    loss = torch.empty_like(D)
+    gX = torch.empty_like(X)
+    _check(LIB.ip_taylor(plan.handle, _ptr(X), _ptr(Dstar), _ptr(D), _ptr(loss), _ptr(gX),
+                         _stream(stream)))
+    return D, loss, gX
