@@ -59,14 +59,15 @@ def touched_points(X, grid):
 
 
 def algorithmic_bytes(wl, touched, real_bytes):
-    """Bytes one step must move at minimum, in the layout the library takes:
-    X read + write (FP64), pinned mask, connectivity (int32), reference arrays
-    l0, (cos, sin) theta0, A0 (real), per-body arrays, u read and f
-    read-modify-write over the touched grid points."""
+    """Bytes one step must move at minimum, in the layout the step reads with a
+    bound reference: X read + write (FP64), pinned mask, the packed element
+    records (four 16-bit local node ids with l0, cos and sin theta0 per edge:
+    32 B in FP64, 24 B in FP32; three ids with A0 per face: 16 B), per-body
+    arrays, u read and f read-modify-write over the touched grid points."""
     N, E, F, B = wl.n_nodes, wl.n_edges, wl.n_faces, wl.n_bodies
     nodes = N * (8 * 3 * 2 + 1)
-    edges = E * (16 + real_bytes * 3)
-    faces = F * (12 + real_bytes)
+    edges = E * (32 if real_bytes == 8 else 24)
+    faces = F * 16
     bodies = B * (8 * 8 + 1 + 8 * 3)      # ks kb kA kV mass V0 V A, closed, offsets
     grid = touched * real_bytes * 3       # u read, f read + write
     return nodes + edges + faces + bodies + grid
@@ -202,7 +203,9 @@ def main():
         rdt = N.real_dtype(precision)
         u = torch.as_tensor(u_host).to(dev, rdt)
         plan = N.Plan(wl, wl.grid, precision)
-        ref = N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev))
+        # the reference is bound once (packed element records); steps pass None
+        N.ip_plan_bind_reference(plan, N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev)))
+        ref = None
         k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
         X = torch.as_tensor(wl.X).to(dev)
         f = torch.zeros(u.shape, dtype=rdt, device=dev)

@@ -141,6 +141,20 @@ ip_status ip_plan_properties(const ip_plan *plan, int64_t props[4]);
 ip_status ip_reference_from(ip_plan *plan, const double *Xref, void *l0, void *cs0,
                             void *A0, double *V0, void *stream);
 
+/* Bind a reference to the plan: its arrays are copied (asynchronously on
+ * `stream`; the caller may reuse them once the stream has passed this call)
+ * into plan-owned storage.  Afterwards every entry point that takes an
+ * ip_reference accepts NULL for "the bound reference".  For plans whose step
+ * is fused (ip_plan_properties props[0] = 1) the bound copy is also packed
+ * into per-element records, node ids local to the body with the element's
+ * reference values (32 bytes per edge, 16 per face in FP64), ordered so that
+ * every run of 64 elements touches distinct nodes where the mesh allows; the
+ * fused step reads these records when given NULL, and the caller's arrays in
+ * the caller's order otherwise (same results up to summation order).  Binding
+ * again replaces the bound reference.  The first call allocates the storage
+ * (IP_ERR_OOM on failure); later calls allocate nothing. */
+ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *stream);
+
 /* Interaction-potential forces at positions X (Section 2.3):
  *   W_e = 1/2 ks (l - l0)^2               every edge
  *   W_b = kb (1 - cos(theta - theta0))    every edge with two faces

@@ -62,10 +62,80 @@ void free_plan(ip_plan *p) {
     if (!p) return;
     void *ptrs[] = {p->node_off, p->edge_off, p->face_off, p->faces, p->edges4, p->closed,
                     p->pinned, p->csr_ptr, p->csr_slot, p->slots, p->Fbuf, p->Ubuf,
-                    p->Vbuf, p->Abuf, p->status, p->fused_bodies, p->bwd_dots};
+                    p->Vbuf, p->Abuf, p->status, p->fused_bodies, p->bwd_dots,
+                    p->bref_l0, p->bref_cs0, p->bref_A0, p->bref_V0, p->edge_perm,
+                    p->face_perm, p->edge_rec, p->face_rec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
+}
+
+// Order the elements of one body (local node ids, -1 = none) so that every
+// run of 64 consecutive elements touches each node at most once, where the
+// mesh allows: greedy first fit into groups of 64.  The fused step gives one
+// group to the 64 lanes of an instruction, whose accumulator additions then
+// never meet on one node.
+void conflict_free_order(int count, int width, const int32_t *elem, int n_nodes,
+                         std::vector<std::vector<int32_t>> &node_groups,
+                         std::vector<int32_t> &order) {
+    constexpr int G = 64;
+    for (int v = 0; v < n_nodes; ++v) node_groups[v].clear();
+    std::vector<std::vector<int32_t>> groups;
+    size_t g0 = 0;
+    for (int e = 0; e < count; ++e) {
+        size_t g = g0;
+        for (;; ++g) {
+            if (g == groups.size()) groups.emplace_back();
+            if ((int)groups[g].size() >= G) continue;
+            bool clash = false;
+            for (int r = 0; r < width && !clash; ++r) {
+                const int v = elem[e * width + r];
+                if (v < 0) continue;
+                for (int32_t gg : node_groups[v])
+                    if ((size_t)gg == g) {
+                        clash = true;
+                        break;
+                    }
+            }
+            if (!clash) break;
+        }
+        groups[g].push_back(e);
+        for (int r = 0; r < width; ++r) {
+            const int v = elem[e * width + r];
+            if (v >= 0) node_groups[v].push_back((int32_t)g);
+        }
+        while (g0 < groups.size() && (int)groups[g0].size() >= G) ++g0;
+    }
+    order.clear();
+    for (auto &g : groups) order.insert(order.end(), g.begin(), g.end());
+}
+
+// Packed-order permutations of every body's edges and faces (fused plans).
+ip_status build_packed_order(ip_plan *p, const ip_mesh *m) {
+    std::vector<int32_t> eperm(p->E), fperm(p->F), loc, order;
+    std::vector<std::vector<int32_t>> node_groups;
+    for (int b = 0; b < p->B; ++b) {
+        const int64_t n0 = m->node_off[b], n1 = m->node_off[b + 1];
+        const int64_t e0 = m->edge_off[b], e1 = m->edge_off[b + 1];
+        const int64_t f0 = m->face_off[b], f1 = m->face_off[b + 1];
+        if ((int64_t)node_groups.size() < n1 - n0) node_groups.resize(n1 - n0);
+        loc.resize(4 * (e1 - e0));
+        for (int64_t e = e0; e < e1; ++e)
+            for (int r = 0; r < 4; ++r) {
+                const int32_t v = m->edges4[4 * e + r];
+                loc[4 * (e - e0) + r] = v < 0 ? -1 : (int32_t)(v - n0);
+            }
+        conflict_free_order((int)(e1 - e0), 4, loc.data(), (int)(n1 - n0), node_groups, order);
+        for (int64_t r = 0; r < e1 - e0; ++r) eperm[e0 + r] = (int32_t)(e0 + order[r]);
+        loc.resize(3 * (f1 - f0));
+        for (int64_t f = f0; f < f1; ++f)
+            for (int r = 0; r < 3; ++r) loc[3 * (f - f0) + r] = (int32_t)(m->faces[3 * f + r] - n0);
+        conflict_free_order((int)(f1 - f0), 3, loc.data(), (int)(n1 - n0), node_groups, order);
+        for (int64_t r = 0; r < f1 - f0; ++r) fperm[f0 + r] = (int32_t)(f0 + order[r]);
+    }
+    IP_TRY(upload(&p->edge_perm, eperm.data(), eperm.size()));
+    IP_TRY(upload(&p->face_perm, fperm.data(), fperm.size()));
+    return IP_OK;
 }
 
 ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_precision prec) {
@@ -164,8 +234,11 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
 
     // fused step eligibility: every body fits one workgroup's registers and LDS
     int max_n = 0;
-    for (int b = 0; b < B; ++b)
+    int64_t max_f = 0;
+    for (int b = 0; b < B; ++b) {
         max_n = std::max(max_n, (int)(m->node_off[b + 1] - m->node_off[b]));
+        max_f = std::max(max_f, m->face_off[b + 1] - m->face_off[b]);
+    }
     int lds_optin = 0;
     IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin,
                                        p->device));
@@ -176,7 +249,8 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
     // are placed (1 KB kept for the kernel's static shared memory)
     const long long tile_bytes =
         ((long long)lds_optin - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
-    p->fused_all = B > 0 && max_n <= kStepThreads * kStepNodesPerThread && tile_bytes >= 4096;
+    p->fused_all = B > 0 && max_n <= kStepThreads * kStepNodesPerThread &&
+                   max_f <= (int64_t)kStepThreads * kStepFacesPerThread && tile_bytes >= 4096;
     p->fused_tile_bytes = p->fused_all ? (int)std::min<long long>(tile_bytes, 1 << 20) : 0;
     if (p->fused_all) {
         std::vector<int32_t> order(B);
@@ -187,6 +261,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
         p->fused_nmax = nmax;
         p->n_fused = B;
         IP_TRY(upload(&p->fused_bodies, order.data(), B));
+        IP_TRY(build_packed_order(p, m));
         IP_TRY(prepare_step_fused(p));
     }
     IP_HIP_CHECK(hipDeviceSynchronize());
@@ -201,9 +276,14 @@ ip_status check_plan(const ip_plan *p) {
     return IP_OK;
 }
 
-ip_status check_ref_k(const ip_plan *p, const ip_reference *ref, const ip_constants *k,
+// A NULL reference means the one bound to the plan; `ref` is resolved in place.
+ip_status check_ref_k(const ip_plan *p, const ip_reference *&ref, const ip_constants *k,
                       bool need_mass) {
-    if (!ref || !k) return arg_error("reference or constants is NULL");
+    if (!ref) {
+        if (!p->ref_bound) return arg_error("reference is NULL and none is bound to the plan");
+        ref = &p->bref;
+    }
+    if (!k) return arg_error("constants is NULL");
     if ((p->E > 0 && (!ref->l0 || !ref->cs0)) || (p->F > 0 && !ref->A0) ||
         (p->B > 0 && !ref->V0))
         return arg_error("reference array is NULL");
@@ -274,6 +354,46 @@ ip_status ip_reference_from(ip_plan *plan, const double *Xref, void *l0, void *c
     hipStream_t s = (hipStream_t)stream;
     IP_TRY(launch_geometry(plan, Xref, V0, plan->Abuf, s));
     return launch_reference(plan, Xref, l0, cs0, A0, s);
+}
+
+ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!ref) return arg_error("reference is NULL");
+    if ((plan->E > 0 && (!ref->l0 || !ref->cs0)) || (plan->F > 0 && !ref->A0) ||
+        (plan->B > 0 && !ref->V0))
+        return arg_error("reference array is NULL");
+    const size_t rs = plan->real_size();
+    if (!aligned(ref->l0, rs) || !aligned(ref->cs0, rs) || !aligned(ref->A0, rs) ||
+        !aligned(ref->V0, 8))
+        return arg_error("misaligned reference array");
+    if (!plan->bref_V0 && plan->B > 0) {
+        IP_TRY(alloc_bytes(&plan->bref_l0, (size_t)plan->E * rs));
+        IP_TRY(alloc_bytes(&plan->bref_cs0, (size_t)plan->E * 2 * rs));
+        IP_TRY(alloc_bytes(&plan->bref_A0, (size_t)plan->F * rs));
+        IP_TRY(upload(&plan->bref_V0, (const double *)nullptr, plan->B));
+        if (plan->fused_all) {
+            const size_t er = plan->prec == IP_F64 ? sizeof(EdgeRec<double>) : sizeof(EdgeRec<float>);
+            IP_TRY(alloc_bytes(&plan->edge_rec, (size_t)plan->E * er));
+            IP_TRY(alloc_bytes(&plan->face_rec, (size_t)plan->F * sizeof(FaceRec<double>)));
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->E > 0) {
+        IP_HIP_CHECK(hipMemcpyAsync(plan->bref_l0, ref->l0, (size_t)plan->E * rs,
+                                    hipMemcpyDeviceToDevice, s));
+        IP_HIP_CHECK(hipMemcpyAsync(plan->bref_cs0, ref->cs0, (size_t)plan->E * 2 * rs,
+                                    hipMemcpyDeviceToDevice, s));
+    }
+    if (plan->F > 0)
+        IP_HIP_CHECK(hipMemcpyAsync(plan->bref_A0, ref->A0, (size_t)plan->F * rs,
+                                    hipMemcpyDeviceToDevice, s));
+    if (plan->B > 0)
+        IP_HIP_CHECK(hipMemcpyAsync(plan->bref_V0, ref->V0, (size_t)plan->B * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s));
+    plan->bref = ip_reference{plan->bref_l0, plan->bref_cs0, plan->bref_A0, plan->bref_V0};
+    if (plan->fused_all) IP_TRY(launch_pack_reference(plan, s));
+    plan->ref_bound = true;
+    return IP_OK;
 }
 
 ip_status ip_forces(ip_plan *plan, const double *X, const ip_reference *ref,

@@ -59,12 +59,14 @@ __device__ __forceinline__ vec3<T> to(const vec3<S> &a) {
 // h1..h4 are the hinge forces on v1..v4.  The angle (normals, cos, sin,
 // dW/dtheta) is evaluated in P: with FP32 edge vectors sin(theta) would carry
 // ~1e-7 absolute error while theta - theta0 is ~1e-3 on fine smooth meshes.
-// Returns true if the element is degenerate (zero length or zero-area wing).
+// x3 and x4 are read only when `hinge` (an edge on the open boundary of a
+// membrane has no hinge).  Returns true if the element is degenerate (zero
+// length or zero-area wing).
 template <typename P, typename R>
 __device__ __forceinline__ bool edge_parts(const vec3<P> &x1, const vec3<P> &x2,
-                                           const vec3<P> *x3, const vec3<P> *x4, R l0, R c0,
-                                           R s0, double ks, double kb, vec3<R> &fsp, vec3<R> &h1,
-                                           vec3<R> &h2, vec3<R> &h3, vec3<R> &h4) {
+                                           const vec3<P> &x3, const vec3<P> &x4, bool hinge, R l0,
+                                           R c0, R s0, double ks, double kb, vec3<R> &fsp,
+                                           vec3<R> &h1, vec3<R> &h2, vec3<R> &h3, vec3<R> &h4) {
     const vec3<R> ev = to<R>(x2 - x1);
     const R le2 = dot(ev, ev);
     const R inv_le = rsq_nr(le2);
@@ -72,8 +74,8 @@ __device__ __forceinline__ bool edge_parts(const vec3<P> &x1, const vec3<P> &x2,
     fsp = ((R)ks * (le - l0) * inv_le) * ev;
     h1 = h2 = h3 = h4 = vec3<R>{(R)0, (R)0, (R)0};
     bool bad = !(le2 > (R)0);
-    if (x3 && x4) {
-        const vec3<P> evd = x2 - x1, d3d = *x3 - x1, d4d = *x4 - x1;
+    if (hinge) {
+        const vec3<P> evd = x2 - x1, d3d = x3 - x1, d4d = x4 - x1;
         const vec3<P> nA = cross(evd, d3d);
         const vec3<P> nB = cross(d4d, evd);
         const P nA2 = dot(nA, nA), nB2 = dot(nB, nB);
@@ -103,11 +105,12 @@ __device__ __forceinline__ bool edge_parts(const vec3<P> &x1, const vec3<P> &x2,
 // Node forces of an edge element: f1 = fsp + h1, f2 = -fsp + h2, f3 = h3, f4 = h4.
 template <typename P, typename R>
 __device__ __forceinline__ bool edge_forces(const vec3<P> &x1, const vec3<P> &x2,
-                                            const vec3<P> *x3, const vec3<P> *x4, R l0, R c0,
-                                            R s0, double ks, double kb, vec3<R> &f1, vec3<R> &f2,
-                                            vec3<R> &f3, vec3<R> &f4) {
+                                            const vec3<P> &x3, const vec3<P> &x4, bool hinge, R l0,
+                                            R c0, R s0, double ks, double kb, vec3<R> &f1,
+                                            vec3<R> &f2, vec3<R> &f3, vec3<R> &f4) {
     vec3<R> fsp, h1, h2;
-    const bool bad = edge_parts<P, R>(x1, x2, x3, x4, l0, c0, s0, ks, kb, fsp, h1, h2, f3, f4);
+    const bool bad =
+        edge_parts<P, R>(x1, x2, x3, x4, hinge, l0, c0, s0, ks, kb, fsp, h1, h2, f3, f4);
     f1 = fsp + h1;
     f2 = h2 - fsp;
     return bad;

@@ -66,8 +66,44 @@ struct ip_plan {
 
     double *bwd_dots = nullptr;   // [2E + 2F] family dot products (reverse step)
 
+    // bound reference (ip_plan_bind_reference): copies in the caller's element
+    // order for the element kernels, and packed records in a conflict-free
+    // order for the fused step
+    bool ref_bound = false;
+    void *bref_l0 = nullptr, *bref_cs0 = nullptr, *bref_A0 = nullptr;  // real, caller order
+    double *bref_V0 = nullptr;
+    ip_reference bref{};
+    int32_t *edge_perm = nullptr;  // [E] packed position -> edge id (same body)
+    int32_t *face_perm = nullptr;  // [F] packed position -> face id (same body)
+    void *edge_rec = nullptr;      // [E] EdgeRec<real>
+    void *face_rec = nullptr;      // [F] FaceRec<real>
+
     size_t real_size() const { return prec == IP_F64 ? sizeof(double) : sizeof(float); }
 };
+
+// Packed element records of a bound reference: node ids local to the body
+// (0xFFFF = no wing) with the element's reference values, one or two vector
+// loads per element.
+constexpr uint16_t kNoNode = 0xFFFF;
+template <typename R>
+struct EdgeRec;
+template <>
+struct alignas(16) EdgeRec<double> {
+    uint16_t v[4];
+    double l0, c0, s0;
+};
+template <>
+struct alignas(8) EdgeRec<float> {
+    uint16_t v[4];
+    float l0, c0, s0, pad;
+};
+template <typename R>
+struct alignas(16) FaceRec {
+    uint16_t v[3], pad;
+    R a0;
+};
+static_assert(sizeof(EdgeRec<double>) == 32 && sizeof(EdgeRec<float>) == 24, "edge record");
+static_assert(sizeof(FaceRec<double>) == 16 && sizeof(FaceRec<float>) == 16, "face record");
 
 // launchers (k_forces.hip / k_transfer.hip); all asynchronous on `s`
 ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s);
@@ -93,10 +129,12 @@ ip_status launch_taylor(ip_plan *p, const double *X, const double *Dstar, double
                         double *gX, hipStream_t s);
 
 // fused step (k_step.hip)
-constexpr int kStepThreads = 1024;
-constexpr int kStepNodesPerThread = 3;
+constexpr int kStepThreads = 768;
+constexpr int kStepNodesPerThread = 4;
+constexpr int kStepFacesPerThread = 8;   // faces held in registers per thread
 size_t step_fused_lds_bytes(int nmax, int tile_bytes);
 ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
+ip_status launch_pack_reference(ip_plan *p, hipStream_t s);
 ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
                             const ip_constants *k, const void *u, void *f, double dt,
                             double *V, double *A, hipStream_t s);

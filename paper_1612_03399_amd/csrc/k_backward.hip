@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_edges_jvp(
         x4 = ldXd(X, T, q.w);
     }
     vec3<dual> fsp, h1, h2, h3, h4;
-    edge_parts<dual, dual>(x1, x2, hinge ? &x3 : nullptr, hinge ? &x4 : nullptr, dual(l0[e]),
+    edge_parts<dual, dual>(x1, x2, x3, x4, hinge, dual(l0[e]),
                            dual(cs0[2 * e]), dual(cs0[2 * e + 1]), ks[b], kb[b], fsp, h1, h2, h3,
                            h4);
     const vec3<dual> f1 = fsp + h1, f2 = h2 - fsp;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_edges_jvp(
         const vec3<double> y1 = {x1.x.v, x1.y.v, x1.z.v}, y2 = {x2.x.v, x2.y.v, x2.z.v},
                            y3 = {x3.x.v, x3.y.v, x3.z.v}, y4 = {x4.x.v, x4.y.v, x4.z.v};
         vec3<double> u0, u1, u2, u3, u4;
-        edge_parts<double, double>(y1, y2, hinge ? &y3 : nullptr, hinge ? &y4 : nullptr, l0[e],
+        edge_parts<double, double>(y1, y2, y3, y4, hinge, l0[e],
                                    cs0[2 * e], cs0[2 * e + 1], 1.0, 1.0, u0, u1, u2, u3, u4);
         const vec3<double> p1 = ldX(P, q.x), p2 = ldX(P, q.y);
         double bend = 0.0;

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
         x4 = ldX(X, q.w);
     }
     vec3<R> f1, f2, f3, f4;
-    const bool bad = edge_forces<double, R>(x1, x2, hinge ? &x3 : nullptr, hinge ? &x4 : nullptr, l0[e],
+    const bool bad = edge_forces<double, R>(x1, x2, x3, x4, hinge, l0[e],
                                     cs0[2 * e], cs0[2 * e + 1], ks[b], kb[b], f1, f2, f3, f4);
     if (bad) atomicOr(status, IP_STATUS_DEGENERATE);
     R *o = slots + 12 * e;

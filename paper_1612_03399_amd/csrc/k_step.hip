@@ -34,6 +34,7 @@ namespace {
 constexpr int NT = kStepThreads;
 constexpr int K = kStepNodesPerThread;
 constexpr int kCountBins = 32;     // occupied cells are ordered by node count (capped)
+constexpr int FK = kStepFacesPerThread;
 
 struct StepArgs {
     double *X;
@@ -51,6 +52,7 @@ struct StepArgs {
     double dt;
     double *V, *A;
     uint32_t *status;
+    const void *erec, *frec; // packed records of the bound reference (packed variant)
     const int32_t *bodies;   // body handled by each workgroup
     int nmax;                // node capacity of the LDS layout
     int tile_bytes;          // bytes of the tile region
@@ -244,7 +246,41 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
             }
 }
 
+// Raw packed records (vector loads) and their fields.
 template <typename R>
+struct RawEdge;
+template <>
+struct RawEdge<double> {
+    int4 a, b;
+    __device__ static RawEdge load(const void *base, int t) {
+        const int4 *p = (const int4 *)base + 2 * (int64_t)t;
+        return {p[0], p[1]};
+    }
+    __device__ int4 ids() const {
+        return {a.x & 0xFFFF, (int)((unsigned)a.x >> 16), a.y & 0xFFFF, (int)((unsigned)a.y >> 16)};
+    }
+    __device__ double l0() const { return __hiloint2double(a.w, a.z); }
+    __device__ double c0() const { return __hiloint2double(b.y, b.x); }
+    __device__ double s0() const { return __hiloint2double(b.w, b.z); }
+};
+template <>
+struct RawEdge<float> {
+    int2 a, b, c;
+    __device__ static RawEdge load(const void *base, int t) {
+        const int2 *p = (const int2 *)base + 3 * (int64_t)t;
+        return {p[0], p[1], p[2]};
+    }
+    __device__ int4 ids() const {
+        return {a.x & 0xFFFF, (int)((unsigned)a.x >> 16), a.y & 0xFFFF, (int)((unsigned)a.y >> 16)};
+    }
+    __device__ float l0() const { return __int_as_float(b.x); }
+    __device__ float c0() const { return __int_as_float(b.y); }
+    __device__ float s0() const { return __int_as_float(c.x); }
+};
+__device__ __forceinline__ double face_a0(const int4 &r, double) { return __hiloint2double(r.w, r.z); }
+__device__ __forceinline__ float face_a0(const int4 &r, float) { return __int_as_float(r.z); }
+
+template <typename R, bool PK>
 __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[NT / 64];
@@ -279,21 +315,66 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     uint16_t *occ_cnt = occ_start + a.nmax;                           // [nmax] node count
     bool bad = false;
 
+    // ---- faces of this thread, loaded first so that their latency overlaps
+    // the position copy; kept in registers for P1 and P2 ----
+    // Element order: in the packed variant the records are already in an
+    // order where each run of 64 touches distinct nodes, and lane t takes
+    // element t.  Otherwise lane l of every wave takes the contiguous strip
+    // [l S, (l+1) S) of the body's elements (S = ceil(count / 64)) and the
+    // waves step through it together, so the 64 lanes of one instruction
+    // touch elements S apart (elements in mesh order share nodes, up to 6
+    // lanes on one address).
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = NT / 64;
+    const int Sf = (F + 63) >> 6;
+    int fi[FK][3];
+    R fa0[FK];
+    unsigned fmask = 0;
+#pragma unroll
+    for (int s = 0; s < FK; ++s) {
+        int t;
+        bool ok;
+        if constexpr (PK) {
+            t = tid + s * NT;
+            ok = t < F;
+        } else {
+            const int q = wave + s * NW;
+            t = lane * Sf + q;
+            ok = q < Sf && t < F;
+        }
+        fi[s][0] = fi[s][1] = fi[s][2] = 0;
+        fa0[s] = (R)1;
+        if (ok) {
+            fmask |= 1u << s;
+            if constexpr (PK) {
+                const int4 r = ((const int4 *)a.frec)[f0 + t];
+                fi[s][0] = r.x & 0xFFFF;
+                fi[s][1] = (int)((unsigned)r.x >> 16);
+                fi[s][2] = r.y & 0xFFFF;
+                fa0[s] = face_a0(r, (R)0);
+            } else {
+                const int32_t *fb = a.faces + 3 * f0;
+                fi[s][0] = fb[3 * t] - (int)n0;
+                fi[s][1] = fb[3 * t + 1] - (int)n0;
+                fi[s][2] = fb[3 * t + 2] - (int)n0;
+                fa0[s] = ((const R *)a.A0)[f0 + t];
+            }
+        }
+    }
+
     // ---- P0: positions ----
     const double *Xb = a.X + 3 * n0;
     copy_to_lds(xs, Xb, 3 * N);
     for (int i = tid; i < 3 * N; i += NT) Fs[i] = 0.0;
     __syncthreads();
-    double xr[K][3];
     int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         const int j = tid + s * NT;
+        if (j < N) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xr[s][c] = j < N ? xs[3 * j + c] : 0.0;
-            if (j < N) {
-                const int kc = cell_of(xr[s][c], a.inv_h);
+            for (int c = 0; c < 3; ++c) {
+                const int kc = cell_of(xs[3 * j + c], a.inv_h);
                 lo[c] = min(lo[c], kc);
                 hi[c] = max(hi[c], kc);
             }
@@ -309,13 +390,15 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     // ---- P1: volume and area ----
     const vec3<double> anchor = ldx(xs, 0);
     double v6 = 0.0, a2 = 0.0;
-    for (int t = tid; t < F; t += NT) {
-        const int32_t *tr = a.faces + 3 * (f0 + t);
-        double v, ar;
-        face_geometry<double, R>(ldx(xs, tr[0] - (int)n0), ldx(xs, tr[1] - (int)n0),
-                         ldx(xs, tr[2] - (int)n0), anchor, v, ar);
-        v6 += v;
-        a2 += ar;
+#pragma unroll
+    for (int s = 0; s < FK; ++s) {
+        if (fmask & (1u << s)) {
+            double v, ar;
+            face_geometry<double, R>(ldx(xs, fi[s][0]), ldx(xs, fi[s][1]), ldx(xs, fi[s][2]),
+                                     anchor, v, ar);
+            v6 += v;
+            a2 += ar;
+        }
     }
     v6 = block_sum(v6, red);
     a2 = block_sum(a2, red);
@@ -329,76 +412,120 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
 
     // ---- P2: elements -> node accumulators ----
     {
-        const R *A0 = (const R *)a.A0 + f0;
-        const int32_t *fb = a.faces + 3 * f0;
         const R sV = volume_coefficient<R>(a.closed[b] != 0, a.kV[b], Vb, a.V0[b]);
         const double kA = a.kA[b];
-        int nf[3] = {0, 0, 0};
-        R na0 = (R)1;
-        if (tid < F) {
-            nf[0] = fb[3 * tid];
-            nf[1] = fb[3 * tid + 1];
-            nf[2] = fb[3 * tid + 2];
-            na0 = A0[tid];
-        }
-        for (int t = tid; t < F; t += NT) {
-            const int i = nf[0] - (int)n0, j = nf[1] - (int)n0, k = nf[2] - (int)n0;
-            const R a0 = na0;
-            if (t + NT < F) {      // next face's data in flight during this one
-                nf[0] = fb[3 * (t + NT)];
-                nf[1] = fb[3 * (t + NT) + 1];
-                nf[2] = fb[3 * (t + NT) + 2];
-                na0 = A0[t + NT];
+#pragma unroll
+        for (int s = 0; s < FK; ++s) {
+            if (fmask & (1u << s)) {
+                const int i = fi[s][0], j = fi[s][1], k = fi[s][2];
+                vec3<R> gi, gj, gk;
+                bad |= face_forces<double, R>(ldx(xs, i), ldx(xs, j), ldx(xs, k), fa0[s], kA, sV,
+                                              gi, gj, gk);
+                add3(Fs, i, gi);
+                add3(Fs, j, gj);
+                add3(Fs, k, gk);
             }
-            vec3<R> gi, gj, gk;
-            bad |= face_forces<double, R>(ldx(xs, i), ldx(xs, j), ldx(xs, k), a0, kA, sV, gi, gj, gk);
-            add3(Fs, i, gi);
-            add3(Fs, j, gj);
-            add3(Fs, k, gk);
         }
         const R *l0 = (const R *)a.l0 + e0;
         const R *cs0 = (const R *)a.cs0 + 2 * e0;
         const int4 *eb = a.e4 + e0;
         const double ks = a.ks[b], kb = a.kb[b];
-        // edge data two iterations ahead: slot 0 = next, slot 1 = the one after
-        int4 nq[2] = {{0, 0, -1, -1}, {0, 0, -1, -1}};
-        R nl0[2] = {(R)1, (R)1}, nc0[2] = {(R)1, (R)1}, ns0[2] = {(R)0, (R)0};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int t = tid + k * NT;
-            if (t < E) {
-                nq[k] = eb[t];
-                nl0[k] = l0[t];
-                nc0[k] = cs0[2 * t];
-                ns0[k] = cs0[2 * t + 1];
+        if constexpr (PK) {
+            // packed records, two iterations ahead; the next edge's node
+            // positions are read before the current edge's accumulator
+            // additions are issued (waiting for them never waits for those)
+            using Raw = RawEdge<R>;
+            const auto fetch = [&](int t) {
+                Raw r{};
+                if (t < E) r = Raw::load(a.erec, (int)e0 + t);
+                return r;
+            };
+            const auto read_nodes = [&](const int4 &q, vec3<double> &y1, vec3<double> &y2,
+                                        vec3<double> &y3, vec3<double> &y4) {
+                const bool h = q.z != kNoNode && q.w != kNoNode;
+                y1 = ldx(xs, q.x);
+                y2 = ldx(xs, q.y);
+                y3 = ldx(xs, h ? q.z : 0);
+                y4 = ldx(xs, h ? q.w : 0);
+            };
+            Raw rc = fetch(tid), rn = fetch(tid + NT);
+            vec3<double> x1, x2, x3, x4;
+            if (tid < E) read_nodes(rc.ids(), x1, x2, x3, x4);
+            for (int t = tid; t < E; t += NT) {
+                const Raw cur = rc;
+                rc = rn;
+                rn = fetch(t + 2 * NT);
+                const int4 q = cur.ids();
+                const bool hinge = q.z != kNoNode && q.w != kNoNode;
+                vec3<R> f1, f2, f3, f4;
+                bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, cur.l0(), cur.c0(), cur.s0(),
+                                              ks, kb, f1, f2, f3, f4);
+                if (t + NT < E) read_nodes(rc.ids(), x1, x2, x3, x4);
+                add3(Fs, q.x, f1);
+                add3(Fs, q.y, f2);
+                if (hinge) {
+                    add3(Fs, q.z, f3);
+                    add3(Fs, q.w, f4);
+                }
+            }
+        } else {
+        // Edges in the same strip order as the faces.  Software pipeline:
+        // the next edge's node ids are loaded from memory two iterations
+        // ahead (its reference data one ahead), and its node positions are
+        // read from LDS before the current edge's accumulator additions are
+        // issued, so waiting for those reads never waits for the additions.
+        const int Se = (E + 63) >> 6;
+        const int ebase = lane * Se;
+        const auto edge_ids = [&](int qq) {
+            const int t = ebase + qq;
+            return qq < Se && t < E ? eb[t] : int4{(int)n0, (int)n0, -1, -1};
+        };
+        const auto read_nodes = [&](const int4 &q, vec3<double> &y1, vec3<double> &y2,
+                                    vec3<double> &y3, vec3<double> &y4) {
+            const bool h = q.z >= 0 && q.w >= 0;
+            y1 = ldx(xs, q.x - (int)n0);
+            y2 = ldx(xs, q.y - (int)n0);
+            y3 = ldx(xs, h ? q.z - (int)n0 : 0);
+            y4 = ldx(xs, h ? q.w - (int)n0 : 0);
+        };
+        int4 qc = edge_ids(wave), qn = edge_ids(wave + NW);
+        vec3<double> x1, x2, x3, x4;
+        read_nodes(qc, x1, x2, x3, x4);
+        R el0 = (R)1, c0 = (R)1, s0 = (R)0;
+        if (wave < Se && ebase + wave < E) {
+            el0 = l0[ebase + wave];
+            c0 = cs0[2 * (ebase + wave)];
+            s0 = cs0[2 * (ebase + wave) + 1];
+        }
+        for (int qe = wave; qe < Se; qe += NW) {
+            const bool live = ebase + qe < E;
+            const int4 q = qc;
+            qc = qn;
+            qn = edge_ids(qe + 2 * NW);
+            const R el0c = el0, c0c = c0, s0c = s0;
+            {
+                const int t = ebase + qe + NW;
+                if (qe + NW < Se && t < E) {
+                    el0 = l0[t];
+                    c0 = cs0[2 * t];
+                    s0 = cs0[2 * t + 1];
+                }
+            }
+            const bool hinge = q.z >= 0 && q.w >= 0;
+            vec3<R> f1, f2, f3, f4;
+            if (live)
+                bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, el0c, c0c, s0c, ks, kb, f1,
+                                              f2, f3, f4);
+            if (qe + NW < Se) read_nodes(qc, x1, x2, x3, x4);
+            if (live) {
+                add3(Fs, q.x - (int)n0, f1);
+                add3(Fs, q.y - (int)n0, f2);
+                if (hinge) {
+                    add3(Fs, q.z - (int)n0, f3);
+                    add3(Fs, q.w - (int)n0, f4);
+                }
             }
         }
-        for (int t = tid; t < E; t += NT) {
-            const int4 q = nq[0];
-            const R el0 = nl0[0], c0 = nc0[0], s0 = ns0[0];
-            nq[0] = nq[1];
-            nl0[0] = nl0[1];
-            nc0[0] = nc0[1];
-            ns0[0] = ns0[1];
-            if (t + 2 * NT < E) {
-                nq[1] = eb[t + 2 * NT];
-                nl0[1] = l0[t + 2 * NT];
-                nc0[1] = cs0[2 * (t + 2 * NT)];
-                ns0[1] = cs0[2 * (t + 2 * NT) + 1];
-            }
-            const int i1 = q.x - (int)n0, i2 = q.y - (int)n0;
-            const bool hinge = q.z >= 0 && q.w >= 0;
-            const int i3 = hinge ? q.z - (int)n0 : 0, i4 = hinge ? q.w - (int)n0 : 0;
-            const vec3<double> x3 = ldx(xs, i3), x4 = ldx(xs, i4);
-            vec3<R> f1, f2, f3, f4;
-            bad |= edge_forces<double, R>(ldx(xs, i1), ldx(xs, i2), hinge ? &x3 : nullptr,
-                                  hinge ? &x4 : nullptr, el0, c0, s0, ks, kb, f1, f2, f3, f4);
-            add3(Fs, i1, f1);
-            add3(Fs, i2, f2);
-            if (hinge) {
-                add3(Fs, i3, f3);
-                add3(Fs, i4, f4);
-            }
         }
     }
     __syncthreads();
@@ -419,10 +546,13 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const int j = tid + s * NT;
-            key[s] = ((cell_of(xr[s][2], a.inv_h) - kmin[2]) * Cy +
-                      (cell_of(xr[s][1], a.inv_h) - kmin[1])) * Cx +
-                     (cell_of(xr[s][0], a.inv_h) - kmin[0]);
-            if (j < N) atomicAdd(hist + key[s], 1);
+            key[s] = 0;
+            if (j < N) {
+                key[s] = ((cell_of(xs[3 * j + 2], a.inv_h) - kmin[2]) * Cy +
+                          (cell_of(xs[3 * j + 1], a.inv_h) - kmin[1])) * Cx +
+                         (cell_of(xs[3 * j], a.inv_h) - kmin[0]);
+                atomicAdd(hist + key[s], 1);
+            }
         }
         __syncthreads();
         int *occ_idx = hist + C;
@@ -471,14 +601,17 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
                 occ_cnt[r] = (uint16_t)ocn[s];
             }
         }
-        double fr[K][3];
+        double xr[K][3], fr[K][3];
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const int j = tid + s * NT;
             if (j < N) {
                 pos[s] = atomicAdd(hist + key[s], 1);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) fr[s][c] = Fs[3 * j + c];
+                for (int c = 0; c < 3; ++c) {
+                    xr[s][c] = xs[3 * j + c];
+                    fr[s][c] = Fs[3 * j + c];
+                }
             }
         }
         __syncthreads();
@@ -527,15 +660,12 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
                 }
                 __syncthreads();
             } else {
-#pragma unroll
-                for (int s = 0; s < K; ++s) {
-                    const int j = tid + s * NT;
-                    if (j >= N) continue;
+                for (int p = tid; p < N; p += NT) {
                     R wx[3], wy[3], wz[3];
-                    const int cx = delta3<R>(xr[s][0] * a.inv_h - mac_off(d, 0), wx);
-                    const int cy = delta3<R>(xr[s][1] * a.inv_h - mac_off(d, 1), wy);
-                    const int cz = delta3<R>(xr[s][2] * a.inv_h - mac_off(d, 2), wz);
-                    const R fv = (R)(Fs[3 * pos[s] + d] * a.inv_h3);
+                    const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
+                    const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
+                    const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
+                    const R fv = (R)(Fs[3 * p + d] * a.inv_h3);
                     for (int z = 0; z < 3; ++z)
                         for (int y = 0; y < 3; ++y) {
                             R *row = fd + wrapi(cz - 1 + z, a.nz) * a.plane +
@@ -550,14 +680,10 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     }
 
     // ---- P5: interpolation and update, one lattice (= one component) at a time ----
+    // Nodes are visited in work order (cell order when sorted); the new
+    // coordinate d replaces F_d in Fs, which nothing reads after this lattice.
     const double cm = a.dt * a.dt / a.mass[b];
-    bool pinned[K];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const int j = tid + s * NT;
-        pinned[s] = j < N && a.pinned[n0 + j];
-    }
-    __syncthreads();      // every thread is done reading xs (spreading)
+    __syncthreads();      // every thread is done with spreading
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const R *ud = (const R *)a.u + d * a.field;
@@ -565,14 +691,12 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
             stage_tile(utile, ud, tg);
             __syncthreads();
         }
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int j = tid + s * NT;
-            if (j >= N) continue;
+        for (int p = tid; p < N; p += NT) {
             R wx[3], wy[3], wz[3];
-            const int cx = delta3<R>(xr[s][0] * a.inv_h - mac_off(d, 0), wx);
-            const int cy = delta3<R>(xr[s][1] * a.inv_h - mac_off(d, 1), wy);
-            const int cz = delta3<R>(xr[s][2] * a.inv_h - mac_off(d, 2), wz);
+            const double xd = xs[3 * p + d];
+            const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
+            const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
+            const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
             R acc = 0;
             if (use_tile) {
                 const int lx = cx - kmin[0], ly = cy - kmin[1], lz = cz - kmin[2];
@@ -599,20 +723,96 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
                                 wx[2] * row[wrapi(cx + 1, a.nx)]);
                     }
             }
-            const double fd = Fs[3 * pos[s] + d];
+            const double fd = Fs[3 * p + d];
             if (!isfinite(fd) || !isfinite((double)acc)) atomicOr(a.status, IP_STATUS_NONFINITE);
-            // new position staged in xs (free once spreading is done), in the
-            // original node order, and written to memory once below
-            xs[3 * j + d] = pinned[s] ? xr[s][d] : xr[s][d] + a.dt * (double)acc + cm * (double)(R)fd;
+            Fs[3 * p + d] = xd + a.dt * (double)acc + cm * (double)(R)fd;
         }
         if (use_tile) __syncthreads();
+    }
+    __syncthreads();
+    // back to node order (pinned nodes keep their position), staged in xs and
+    // written to memory once, coalesced
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int j = tid + s * NT;
+        if (j < N) {
+            const bool pin = a.pinned[n0 + j] != 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double v = pin ? Xb[3 * j + c] : Fs[3 * pos[s] + c];
+                xs[3 * j + c] = v;
+            }
+        }
     }
     __syncthreads();
     for (int i = tid; i < 3 * N; i += NT) a.X[3 * n0 + i] = xs[i];
     if (bad) atomicOr(a.status, IP_STATUS_DEGENERATE);
 }
 
+// Packed records of a bound reference, in the plan's conflict-free order.
+template <typename R>
+__global__ void k_pack_edges(const int32_t *__restrict__ perm, const int4 *__restrict__ e4,
+                             const int64_t *__restrict__ edge_off,
+                             const int64_t *__restrict__ node_off, int B, int64_t E,
+                             const R *__restrict__ l0, const R *__restrict__ cs0,
+                             EdgeRec<R> *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= E) return;
+    const int e = perm[r];
+    const int64_t n0 = node_off[body_of(edge_off, B, r)];
+    const int4 q = e4[e];
+    EdgeRec<R> o{};
+    o.v[0] = (uint16_t)(q.x - n0);
+    o.v[1] = (uint16_t)(q.y - n0);
+    o.v[2] = q.z >= 0 ? (uint16_t)(q.z - n0) : kNoNode;
+    o.v[3] = q.w >= 0 ? (uint16_t)(q.w - n0) : kNoNode;
+    o.l0 = l0[e];
+    o.c0 = cs0[2 * (int64_t)e];
+    o.s0 = cs0[2 * (int64_t)e + 1];
+    out[r] = o;
+}
+
+template <typename R>
+__global__ void k_pack_faces(const int32_t *__restrict__ perm, const int32_t *__restrict__ faces,
+                             const int64_t *__restrict__ face_off,
+                             const int64_t *__restrict__ node_off, int B, int64_t F,
+                             const R *__restrict__ A0, FaceRec<R> *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= F) return;
+    const int f = perm[r];
+    const int64_t n0 = node_off[body_of(face_off, B, r)];
+    FaceRec<R> o{};
+    o.v[0] = (uint16_t)(faces[3 * (int64_t)f] - n0);
+    o.v[1] = (uint16_t)(faces[3 * (int64_t)f + 1] - n0);
+    o.v[2] = (uint16_t)(faces[3 * (int64_t)f + 2] - n0);
+    o.a0 = A0[f];
+    out[r] = o;
+}
+
+template <typename R>
+void pack_reference(ip_plan *p, hipStream_t s) {
+    const int t = 256;
+    if (p->E > 0)
+        hipLaunchKernelGGL(k_pack_edges<R>, dim3((unsigned)((p->E + t - 1) / t)), dim3(t), 0, s,
+                           p->edge_perm, (const int4 *)p->edges4, p->edge_off, p->node_off, p->B,
+                           p->E, (const R *)p->bref_l0, (const R *)p->bref_cs0,
+                           (EdgeRec<R> *)p->edge_rec);
+    if (p->F > 0)
+        hipLaunchKernelGGL(k_pack_faces<R>, dim3((unsigned)((p->F + t - 1) / t)), dim3(t), 0, s,
+                           p->face_perm, p->faces, p->face_off, p->node_off, p->B, p->F,
+                           (const R *)p->bref_A0, (FaceRec<R> *)p->face_rec);
+}
+
 }  // namespace
+
+ip_status launch_pack_reference(ip_plan *p, hipStream_t s) {
+    if (p->prec == IP_F64)
+        pack_reference<double>(p, s);
+    else
+        pack_reference<float>(p, s);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
 
 size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
     // xs + Fs (FP64), the tile region, the occupied-cell list (start, count)
@@ -621,12 +821,12 @@ size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
 
 ip_status prepare_step_fused(ip_plan *p) {
     const int lds = (int)step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    if (p->prec == IP_F64)
-        IP_HIP_CHECK(hipFuncSetAttribute((const void *)k_step_fused<double>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    else
-        IP_HIP_CHECK(hipFuncSetAttribute((const void *)k_step_fused<float>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    const void *fn[2] = {p->prec == IP_F64 ? (const void *)k_step_fused<double, false>
+                                           : (const void *)k_step_fused<float, false>,
+                         p->prec == IP_F64 ? (const void *)k_step_fused<double, true>
+                                           : (const void *)k_step_fused<float, true>};
+    for (const void *f : fn)
+        IP_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return IP_OK;
 }
 
@@ -668,11 +868,22 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
     a.bodies = p->fused_bodies;
     a.nmax = p->fused_nmax;
     a.tile_bytes = p->fused_tile_bytes;
+    // the bound reference is read from the packed records
+    const bool packed = ref == &p->bref && p->edge_rec != nullptr && p->face_rec != nullptr;
+    a.erec = p->edge_rec;
+    a.frec = p->face_rec;
     const size_t lds = step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    if (p->prec == IP_F64)
-        hipLaunchKernelGGL(k_step_fused<double>, dim3(p->n_fused), dim3(NT), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_step_fused<float>, dim3(p->n_fused), dim3(NT), lds, s, a);
+    if (p->prec == IP_F64) {
+        if (packed)
+            hipLaunchKernelGGL((k_step_fused<double, true>), dim3(p->n_fused), dim3(NT), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_step_fused<double, false>), dim3(p->n_fused), dim3(NT), lds, s, a);
+    } else {
+        if (packed)
+            hipLaunchKernelGGL((k_step_fused<float, true>), dim3(p->n_fused), dim3(NT), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_step_fused<float, false>), dim3(p->n_fused), dim3(NT), lds, s, a);
+    }
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }

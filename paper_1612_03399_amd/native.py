@@ -70,6 +70,7 @@ def _load():
                     vp, vp],
         "ip_plan_status": [vp, vp, C.POINTER(C.c_uint32)],
         "ip_forces_jvp": [vp, vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp],
+        "ip_plan_bind_reference": [vp, C.POINTER(ip_reference), vp],
         "ip_step_vjp": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, d, vp, vp,
                         vp, vp, vp],
         "ip_taylor": [vp, vp, vp, vp, vp, vp, vp],
@@ -101,6 +102,11 @@ def _ptr(t):
     if isinstance(t, np.ndarray):
         return t.ctypes.data
     raise TypeError(type(t))
+
+
+def _refp(ref):
+    """Pointer to an ip_reference, or NULL for the reference bound to the plan."""
+    return None if ref is None else C.byref(ref.struct())
 
 
 def _stream(stream):
@@ -213,8 +219,8 @@ def ip_forces(plan: Plan, X, ref: Reference, k: Constants, F=None, V=None, A=Non
               stream=None):
     if F is None:
         F = torch.empty(plan.N, 3, dtype=plan.dtype, device=X.device)
-    r, kk = ref.struct(), k.struct()
-    _check(LIB.ip_forces(plan.handle, _ptr(X), C.byref(r), C.byref(kk), _ptr(F), _ptr(V),
+    r, kk = _refp(ref), k.struct()
+    _check(LIB.ip_forces(plan.handle, _ptr(X), r, C.byref(kk), _ptr(F), _ptr(V),
                          _ptr(A), _ptr(W), _stream(stream)))
     return F
 
@@ -233,8 +239,8 @@ def ibm_spread(plan: Plan, X, F, f, stream=None):
 
 def ip_step(plan: Plan, X, ref: Reference, k: Constants, u, f, dt, V=None, A=None,
             stream=None):
-    r, kk = ref.struct(), k.struct()
-    _check(LIB.ip_step(plan.handle, _ptr(X), C.byref(r), C.byref(kk), _ptr(u), _ptr(f),
+    r, kk = _refp(ref), k.struct()
+    _check(LIB.ip_step(plan.handle, _ptr(X), r, C.byref(kk), _ptr(u), _ptr(f),
                        float(dt), _ptr(V), _ptr(A), _stream(stream)))
     return X
 
@@ -250,8 +256,8 @@ def ip_plan_status(plan: Plan, stream=None):
 def ip_forces_jvp(plan: Plan, X, dX, ref: Reference, k: Constants, dF=None, stream=None):
     if dF is None:
         dF = torch.empty_like(X)
-    r, kk = ref.struct(), k.struct()
-    _check(LIB.ip_forces_jvp(plan.handle, _ptr(X), _ptr(dX), C.byref(r), C.byref(kk), _ptr(dF),
+    r, kk = _refp(ref), k.struct()
+    _check(LIB.ip_forces_jvp(plan.handle, _ptr(X), _ptr(dX), r, C.byref(kk), _ptr(dF),
                              _stream(stream)))
     return dF
 
@@ -260,8 +266,8 @@ def ip_step_vjp(plan: Plan, X, ref: Reference, k: Constants, u, dt, lam_next, la
                 gk=None, gu=None, stream=None):
     if lam is None:
         lam = torch.empty_like(lam_next)
-    r, kk = ref.struct(), k.struct()
-    _check(LIB.ip_step_vjp(plan.handle, _ptr(X), C.byref(r), C.byref(kk), _ptr(u), float(dt),
+    r, kk = _refp(ref), k.struct()
+    _check(LIB.ip_step_vjp(plan.handle, _ptr(X), r, C.byref(kk), _ptr(u), float(dt),
                            _ptr(lam_next), _ptr(lam), _ptr(gk), _ptr(gu), _stream(stream)))
     return lam
 
@@ -277,3 +283,10 @@ def ip_taylor(plan: Plan, X, Dstar=None, stream=None):
     _check(LIB.ip_taylor(plan.handle, _ptr(X), _ptr(Dstar), _ptr(D), _ptr(loss), _ptr(gX),
                          _stream(stream)))
     return D, loss, gX
+
+
+def ip_plan_bind_reference(plan: Plan, ref: Reference, stream=None):
+    """Copy (and, for fused plans, pack) a reference into the plan; entry points
+    then accept ref=None for it."""
+    _check(LIB.ip_plan_bind_reference(plan.handle, C.byref(ref.struct()), _stream(stream)))
+    plan.bound_reference = ref      # the copy is asynchronous: keep the source alive

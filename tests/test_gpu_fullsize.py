@@ -22,15 +22,19 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_step(wl, ref, u, precision):
+def gpu_step(wl, ref, u, precision, bound=True):
+    """One ip_step as the bench runs it: reference bound to the plan."""
     rdt = N.real_dtype(precision)
     plan = N.Plan(wl, wl.grid, precision)
     X = dev(wl.X)
     f = torch.zeros(u.shape, dtype=rdt, device=DEV)
     V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
     A = torch.empty_like(V)
-    N.ip_step(plan, X, gpu_reference_from_oracle(ref, precision), constants(wl), dev(u, rdt),
-              f, wl.dt, V=V, A=A)
+    gref = gpu_reference_from_oracle(ref, precision)
+    if bound:
+        N.ip_plan_bind_reference(plan, gref)
+        gref = None
+    N.ip_step(plan, X, gref, constants(wl), dev(u, rdt), f, wl.dt, V=V, A=A)
     code, flags = N.ip_plan_status(plan)
     assert code == N.IP_OK, flags
     return plan, host(X), host(f).astype(np.float64), host(V), host(A)

@@ -115,10 +115,13 @@ def test_interp_spread_parity(case, precision):
     assert rel_inf(host(f).astype(np.float64), want_f) <= TOL[precision]
 
 
+@pytest.mark.parametrize("bound", [False, True], ids=["explicit_ref", "bound_ref"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_step_parity(case, precision):
-    say("step", case, precision)
+def test_step_parity(case, precision, bound):
+    """One step; with a bound reference the fused step reads the packed,
+    conflict-ordered element records instead of the caller's arrays."""
+    say("step", case, precision, "bound" if bound else "explicit")
     wl, ref = build(case, precision)
     dt_ = N.real_dtype(precision)
     u = wl.velocity()
@@ -131,8 +134,11 @@ def test_step_parity(case, precision):
     X = dev(wl.X)
     f = torch.zeros(u.shape, dtype=dt_, device=DEV)
     V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
-    N.ip_step(plan, X, gpu_reference_from_oracle(ref, precision), constants(wl), dev(u, dt_), f,
-              wl.dt, V=V)
+    gref = gpu_reference_from_oracle(ref, precision)
+    if bound:
+        N.ip_plan_bind_reference(plan, gref)
+        gref = None
+    N.ip_step(plan, X, gref, constants(wl), dev(u, dt_), f, wl.dt, V=V)
     code, _ = N.ip_plan_status(plan)
     assert code == N.IP_OK
     # X_new = X + dX is rounded to the spacing of |X| on both sides, so the
@@ -207,3 +213,29 @@ def test_degenerate_face_sets_status():
     assert flags & N.IP_STATUS_DEGENERATE
     code, flags = N.ip_plan_status(plan)      # cleared by the read
     assert code == N.IP_OK and flags == 0
+
+
+def test_bound_reference_entry_points():
+    """Forces, derivatives and the reverse step accept the bound reference;
+    without one bound, a NULL reference is an argument error."""
+    say("bound reference")
+    wl, ref = build("four_L2_32", "f64")
+    plan = N.Plan(wl, wl.grid, "f64")
+    gref = gpu_reference_from_oracle(ref, "f64")
+    k = constants(wl)
+    X = dev(wl.X)
+    with pytest.raises(N.IpibmError) as e:
+        N.ip_forces(plan, X, None, k)
+    assert e.value.code == N.IP_ERR_ARG
+    F1 = host(N.ip_forces(plan, X, gref, k))
+    N.ip_plan_bind_reference(plan, gref)
+    F2 = host(N.ip_forces(plan, X, None, k))
+    assert np.array_equal(F1, F2)
+    dX = dev(np.random.default_rng(4).normal(size=wl.X.shape))
+    assert np.array_equal(host(N.ip_forces_jvp(plan, X, dX, gref, k)),
+                          host(N.ip_forces_jvp(plan, X, dX, None, k)))
+    # rebinding replaces the reference: bind the current shape, forces vanish
+    g2 = N.ip_reference_from(plan, X)
+    N.ip_plan_bind_reference(plan, g2)
+    F3 = host(N.ip_forces(plan, X, None, k))
+    assert np.abs(F3).max() <= 1e-13 * np.abs(F1).max()
