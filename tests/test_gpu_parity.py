@@ -32,6 +32,9 @@ CASES = {
     "drop_L3_64": lambda: W.config0(),
     "sparse_L0_48": sparse_icosahedra,
     "four_L2_32": lambda: W.small_suspension(4, 2, 32),
+    # bench-shaped bodies (level 4, radius 5.12 h): more spreading work items
+    # than a workgroup's lanes, every fused-kernel loop takes several turns
+    "four_L4_128": lambda: W.small_suspension(4, 4, 128, r=0.04),
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
                                          cells_per_unit=64),
