@@ -126,12 +126,19 @@ ip_status ip_plan_destroy(ip_plan *plan);
 /* Sizes: counts[0..3] = bodies, nodes, edges, faces. */
 ip_status ip_plan_sizes(const ip_plan *plan, int64_t counts[4]);
 
-/* Execution properties chosen at plan time: props[0] = 1 if ip_step runs the
- * fused one-workgroup-per-body kernel (every body fits its LDS layout), else 0
- * (separate element, gather, transfer and update kernels); props[1] = nodes of
- * the largest body; props[2] = LDS bytes of the per-body grid tile;
- * props[3] = threads per workgroup of the fused kernel. */
-ip_status ip_plan_properties(const ip_plan *plan, int64_t props[4]);
+/* Execution properties chosen at plan time:
+ *   props[0] = 1 if ip_step runs the fused kernel (one workgroup per work
+ *              unit), 0 if it runs the separate element, gather, transfer
+ *              and update kernels;
+ *   props[1] = nodes of the largest work unit;
+ *   props[2] = LDS bytes of the per-unit grid tile;
+ *   props[3] = threads per workgroup of the fused kernel;
+ *   props[4] = number of work units: a body of at most props[3] x 4 nodes is
+ *              one unit, a larger body is split into patches, each owning a
+ *              compact set of its nodes and carrying every element that
+ *              touches them (with the halo nodes those reach);
+ *   props[5] = number of bodies split into patches. */
+ip_status ip_plan_properties(const ip_plan *plan, int64_t props[6]);
 
 /* Reference state from reference positions Xref[N][3] (Section 2.3 "initial
  * (reference) state").  Writes l0[E], cs0[E][2], A0[F] (real) and V0[B]

@@ -42,12 +42,6 @@ ip_status arg_error(const std::string &m) {
     return IP_ERR_ARG;
 }
 
-#define IP_TRY(expr)                        \
-    do {                                    \
-        ip_status st_ = (expr);             \
-        if (st_ != IP_OK) return st_;       \
-    } while (0)
-
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 ip_status check_offsets(const int64_t *off, int B, const char *name) {
@@ -62,80 +56,14 @@ void free_plan(ip_plan *p) {
     if (!p) return;
     void *ptrs[] = {p->node_off, p->edge_off, p->face_off, p->faces, p->edges4, p->closed,
                     p->pinned, p->csr_ptr, p->csr_slot, p->slots, p->Fbuf, p->Ubuf,
-                    p->Vbuf, p->Abuf, p->status, p->fused_bodies, p->bwd_dots,
-                    p->bref_l0, p->bref_cs0, p->bref_A0, p->bref_V0, p->edge_perm,
-                    p->face_perm, p->edge_rec, p->face_rec};
+                    p->Vbuf, p->Abuf, p->status, p->bwd_dots, p->bref_l0, p->bref_cs0,
+                    p->bref_A0, p->bref_V0, p->wu_body, p->wu_owned, p->wu_noff, p->wu_nodes,
+                    p->wu_eoff, p->wu_foff, p->erec_perm, p->erec_lid, p->frec_perm,
+                    p->frec_lid, p->edge_rec, p->face_rec, p->patched_bodies,
+                    p->patched_units, p->Xstage};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
-}
-
-// Order the elements of one body (local node ids, -1 = none) so that every
-// run of 64 consecutive elements touches each node at most once, where the
-// mesh allows: greedy first fit into groups of 64.  The fused step gives one
-// group to the 64 lanes of an instruction, whose accumulator additions then
-// never meet on one node.
-void conflict_free_order(int count, int width, const int32_t *elem, int n_nodes,
-                         std::vector<std::vector<int32_t>> &node_groups,
-                         std::vector<int32_t> &order) {
-    constexpr int G = 64;
-    for (int v = 0; v < n_nodes; ++v) node_groups[v].clear();
-    std::vector<std::vector<int32_t>> groups;
-    size_t g0 = 0;
-    for (int e = 0; e < count; ++e) {
-        size_t g = g0;
-        for (;; ++g) {
-            if (g == groups.size()) groups.emplace_back();
-            if ((int)groups[g].size() >= G) continue;
-            bool clash = false;
-            for (int r = 0; r < width && !clash; ++r) {
-                const int v = elem[e * width + r];
-                if (v < 0) continue;
-                for (int32_t gg : node_groups[v])
-                    if ((size_t)gg == g) {
-                        clash = true;
-                        break;
-                    }
-            }
-            if (!clash) break;
-        }
-        groups[g].push_back(e);
-        for (int r = 0; r < width; ++r) {
-            const int v = elem[e * width + r];
-            if (v >= 0) node_groups[v].push_back((int32_t)g);
-        }
-        while (g0 < groups.size() && (int)groups[g0].size() >= G) ++g0;
-    }
-    order.clear();
-    for (auto &g : groups) order.insert(order.end(), g.begin(), g.end());
-}
-
-// Packed-order permutations of every body's edges and faces (fused plans).
-ip_status build_packed_order(ip_plan *p, const ip_mesh *m) {
-    std::vector<int32_t> eperm(p->E), fperm(p->F), loc, order;
-    std::vector<std::vector<int32_t>> node_groups;
-    for (int b = 0; b < p->B; ++b) {
-        const int64_t n0 = m->node_off[b], n1 = m->node_off[b + 1];
-        const int64_t e0 = m->edge_off[b], e1 = m->edge_off[b + 1];
-        const int64_t f0 = m->face_off[b], f1 = m->face_off[b + 1];
-        if ((int64_t)node_groups.size() < n1 - n0) node_groups.resize(n1 - n0);
-        loc.resize(4 * (e1 - e0));
-        for (int64_t e = e0; e < e1; ++e)
-            for (int r = 0; r < 4; ++r) {
-                const int32_t v = m->edges4[4 * e + r];
-                loc[4 * (e - e0) + r] = v < 0 ? -1 : (int32_t)(v - n0);
-            }
-        conflict_free_order((int)(e1 - e0), 4, loc.data(), (int)(n1 - n0), node_groups, order);
-        for (int64_t r = 0; r < e1 - e0; ++r) eperm[e0 + r] = (int32_t)(e0 + order[r]);
-        loc.resize(3 * (f1 - f0));
-        for (int64_t f = f0; f < f1; ++f)
-            for (int r = 0; r < 3; ++r) loc[3 * (f - f0) + r] = (int32_t)(m->faces[3 * f + r] - n0);
-        conflict_free_order((int)(f1 - f0), 3, loc.data(), (int)(n1 - n0), node_groups, order);
-        for (int64_t r = 0; r < f1 - f0; ++r) fperm[f0 + r] = (int32_t)(f0 + order[r]);
-    }
-    IP_TRY(upload(&p->edge_perm, eperm.data(), eperm.size()));
-    IP_TRY(upload(&p->face_perm, fperm.data(), fperm.size()));
-    return IP_OK;
 }
 
 ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_precision prec) {
@@ -232,37 +160,72 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
     IP_TRY(upload(&p->status, (const uint32_t *)nullptr, 1));
     IP_HIP_CHECK(hipMemset(p->status, 0, sizeof(uint32_t)));
 
-    // fused step eligibility: every body fits one workgroup's registers and LDS
-    int max_n = 0;
-    int64_t max_f = 0;
-    for (int b = 0; b < B; ++b) {
-        max_n = std::max(max_n, (int)(m->node_off[b + 1] - m->node_off[b]));
-        max_f = std::max(max_f, m->face_off[b + 1] - m->face_off[b]);
-    }
+    // fused step: work units (whole bodies, patches of larger ones) that fit
+    // one workgroup's registers and LDS
     int lds_optin = 0;
     IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin,
                                        p->device));
     if (lds_optin <= 0) IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin,
                                      hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
-    const int nmax = std::max(max_n, 1);
-    // LDS left for the grid tile once positions, accumulators and the cell list
-    // are placed (1 KB kept for the kernel's static shared memory)
-    const long long tile_bytes =
-        ((long long)lds_optin - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
-    p->fused_all = B > 0 && max_n <= kStepThreads * kStepNodesPerThread &&
-                   max_f <= (int64_t)kStepThreads * kStepFacesPerThread && tile_bytes >= 4096;
-    p->fused_tile_bytes = p->fused_all ? (int)std::min<long long>(tile_bytes, 1 << 20) : 0;
-    if (p->fused_all) {
-        std::vector<int32_t> order(B);
-        for (int b = 0; b < B; ++b) order[b] = b;
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-            return m->node_off[x + 1] - m->node_off[x] > m->node_off[y + 1] - m->node_off[y];
-        });
-        p->fused_nmax = nmax;
-        p->n_fused = B;
-        IP_TRY(upload(&p->fused_bodies, order.data(), B));
-        IP_TRY(build_packed_order(p, m));
-        IP_TRY(prepare_step_fused(p));
+    const int unit_nodes = kStepThreads * kStepNodesPerThread;
+    const int unit_faces = kStepThreads * kStepFacesPerThread;
+    WorkUnits wu;
+    if (B > 0 && build_work_units(m, unit_nodes, unit_faces, kPatchOwned, wu)) {
+        int nmax = 1;
+        for (const auto &u : wu.units) nmax = std::max(nmax, u.n_nodes);
+        // LDS left for the grid tile once positions, accumulators and the
+        // cell list are placed (1 KB kept for the kernel's static LDS)
+        const long long tile_bytes =
+            ((long long)lds_optin - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
+        if (tile_bytes >= 4096) {
+            p->fused_all = true;
+            p->fused_nmax = nmax;
+            p->fused_tile_bytes = (int)std::min<long long>(tile_bytes, 1 << 20);
+            const int W = (int)wu.units.size();
+            p->n_units = W;
+            // ranges as (begin, end) pairs: units are stored largest first,
+            // their lists in build order
+            std::vector<int32_t> body(W), owned(W), pb, pu;
+            std::vector<int64_t> n2(2 * W), e2(2 * W), f2(2 * W);
+            std::vector<char> patched(B, 0);
+            for (int w = 0; w < W; ++w) {
+                const auto &u = wu.units[w];
+                body[w] = u.body;
+                owned[w] = u.owned;
+                n2[2 * w] = u.node_begin;
+                n2[2 * w + 1] = u.node_end;
+                e2[2 * w] = u.edge_begin;
+                e2[2 * w + 1] = u.edge_end;
+                f2[2 * w] = u.face_begin;
+                f2[2 * w + 1] = u.face_end;
+                if (u.node_end > u.node_begin) {
+                    pu.push_back(w);
+                    if (!patched[u.body]) pb.push_back(u.body);
+                    patched[u.body] = 1;
+                }
+            }
+            IP_TRY(upload(&p->wu_body, body.data(), W));
+            IP_TRY(upload(&p->wu_owned, owned.data(), W));
+            IP_TRY(upload(&p->wu_noff, n2.data(), 2 * W));
+            IP_TRY(upload(&p->wu_eoff, e2.data(), 2 * W));
+            IP_TRY(upload(&p->wu_foff, f2.data(), 2 * W));
+            IP_TRY(upload(&p->wu_nodes, wu.nodes.data(), wu.nodes.size()));
+            p->n_erec = (int64_t)wu.edge_perm.size();
+            p->n_frec = (int64_t)wu.face_perm.size();
+            IP_TRY(upload(&p->erec_perm, wu.edge_perm.data(), wu.edge_perm.size()));
+            IP_TRY(upload(&p->erec_lid, wu.edge_lid.data(), wu.edge_lid.size()));
+            IP_TRY(upload(&p->frec_perm, wu.face_perm.data(), wu.face_perm.size()));
+            IP_TRY(upload(&p->frec_lid, wu.face_lid.data(), wu.face_lid.size()));
+            const size_t er = p->prec == IP_F64 ? sizeof(EdgeRec<double>) : sizeof(EdgeRec<float>);
+            IP_TRY(alloc_bytes(&p->edge_rec, (size_t)p->n_erec * er));
+            IP_TRY(alloc_bytes(&p->face_rec, (size_t)p->n_frec * sizeof(FaceRec<double>)));
+            p->n_patched_bodies = (int32_t)pb.size();
+            p->n_patched_units = (int32_t)pu.size();
+            IP_TRY(upload(&p->patched_bodies, pb.data(), pb.size()));
+            IP_TRY(upload(&p->patched_units, pu.data(), pu.size()));
+            if (!pb.empty()) IP_TRY(alloc_bytes((void **)&p->Xstage, (size_t)N * 3 * sizeof(double)));
+            IP_TRY(prepare_step_fused(p));
+        }
     }
     IP_HIP_CHECK(hipDeviceSynchronize());
     return IP_OK;
@@ -335,12 +298,14 @@ ip_status ip_plan_sizes(const ip_plan *plan, int64_t counts[4]) {
     return IP_OK;
 }
 
-ip_status ip_plan_properties(const ip_plan *plan, int64_t props[4]) {
+ip_status ip_plan_properties(const ip_plan *plan, int64_t props[6]) {
     if (!plan || !props) return arg_error("NULL argument");
     props[0] = plan->fused_all ? 1 : 0;
     props[1] = plan->fused_nmax;
     props[2] = plan->fused_tile_bytes;
     props[3] = kStepThreads;
+    props[4] = plan->n_units;
+    props[5] = plan->n_patched_bodies;
     return IP_OK;
 }
 
@@ -371,11 +336,6 @@ ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *s
         IP_TRY(alloc_bytes(&plan->bref_cs0, (size_t)plan->E * 2 * rs));
         IP_TRY(alloc_bytes(&plan->bref_A0, (size_t)plan->F * rs));
         IP_TRY(upload(&plan->bref_V0, (const double *)nullptr, plan->B));
-        if (plan->fused_all) {
-            const size_t er = plan->prec == IP_F64 ? sizeof(EdgeRec<double>) : sizeof(EdgeRec<float>);
-            IP_TRY(alloc_bytes(&plan->edge_rec, (size_t)plan->E * er));
-            IP_TRY(alloc_bytes(&plan->face_rec, (size_t)plan->F * sizeof(FaceRec<double>)));
-        }
     }
     hipStream_t s = (hipStream_t)stream;
     if (plan->E > 0) {
@@ -391,8 +351,11 @@ ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *s
         IP_HIP_CHECK(hipMemcpyAsync(plan->bref_V0, ref->V0, (size_t)plan->B * sizeof(double),
                                     hipMemcpyDeviceToDevice, s));
     plan->bref = ip_reference{plan->bref_l0, plan->bref_cs0, plan->bref_A0, plan->bref_V0};
-    if (plan->fused_all) IP_TRY(launch_pack_reference(plan, s));
     plan->ref_bound = true;
+    if (plan->fused_all) {
+        IP_TRY(launch_pack_reference(plan, &plan->bref, s));
+        plan->packed = 1;
+    }
     return IP_OK;
 }
 
@@ -434,7 +397,16 @@ ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_co
         return arg_error("misaligned array");
     if (!(dt == dt)) return arg_error("dt is NaN");
     hipStream_t s = (hipStream_t)stream;
-    if (plan->fused_all) return launch_step_fused(plan, X, ref, k, u, f, dt, V, A, s);
+    if (plan->fused_all) {
+        // the records hold the reference the step reads: the bound one, or
+        // this call's explicit one (packed afresh: its contents may change)
+        const bool bound = ref == &plan->bref;
+        if (!bound || plan->packed != 1) {
+            IP_TRY(launch_pack_reference(plan, ref, s));
+            plan->packed = bound ? 1 : 2;
+        }
+        return launch_step_fused(plan, X, ref, k, u, f, dt, V, A, s);
+    }
     IP_TRY(launch_forces(plan, X, ref, k, plan->Fbuf, V, A, nullptr, s));
     IP_TRY(launch_interp(plan, X, u, plan->Ubuf, s));
     if (f) IP_TRY(launch_spread(plan, X, plan->Fbuf, f, s));

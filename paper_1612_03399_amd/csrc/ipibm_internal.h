@@ -15,6 +15,13 @@
 // ----------------------------------------------------------------------------
 void ipibm_set_error(const std::string &msg);
 
+// Return the status of `expr` if it is not IP_OK.
+#define IP_TRY(expr)                        \
+    do {                                    \
+        ip_status st_ = (expr);             \
+        if (st_ != IP_OK) return st_;       \
+    } while (0)
+
 #define IP_HIP_CHECK(expr)                                                        \
     do {                                                                          \
         hipError_t e_ = (expr);                                                   \
@@ -57,26 +64,41 @@ struct ip_plan {
     double *Abuf = nullptr;       // [B]
     uint32_t *status = nullptr;   // device status word
 
-    // fused step: one workgroup per body when every body fits the LDS layout
+    // fused step: one workgroup per work unit (a whole body, or a patch of a
+    // larger one: owned nodes plus the halo its elements reach)
     bool fused_all = false;
-    int fused_nmax = 0;           // largest body (nodes)
-    int n_fused = 0;
-    int fused_tile_bytes = 0;     // LDS bytes for the per-body grid tile
-    int32_t *fused_bodies = nullptr;  // [n_fused] body ids, largest first
+    int fused_nmax = 0;           // largest work unit (nodes, owned + halo)
+    int fused_tile_bytes = 0;     // LDS bytes for the per-unit grid tile
+    int32_t n_units = 0;
+    int32_t *wu_body = nullptr;   // [n_units] body of each unit, largest unit first
+    int32_t *wu_owned = nullptr;  // [n_units] owned nodes
+    int64_t *wu_noff = nullptr;   // [n_units][2] node-list range (empty: whole body)
+    int32_t *wu_nodes = nullptr;  // global ids of patch nodes, owned first
+    int64_t *wu_eoff = nullptr;   // [n_units][2] edge-record range
+    int64_t *wu_foff = nullptr;   // [n_units][2] face-record range
+    int64_t n_erec = 0, n_frec = 0;
+    int32_t *erec_perm = nullptr; // [n_erec] edge id of each record
+    uint16_t *erec_lid = nullptr; // [n_erec][4] unit-local node ids (kNoNode: none)
+    int32_t *frec_perm = nullptr; // [n_frec] face id of each record
+    uint16_t *frec_lid = nullptr; // [n_frec][4] unit-local node ids, last unused
+    void *edge_rec = nullptr;     // [n_erec] EdgeRec<real>
+    void *face_rec = nullptr;     // [n_frec] FaceRec<real>
+    int packed = 0;               // records hold: 0 nothing, 1 the bound reference,
+                                  // 2 the last explicit reference
+    int32_t n_patched_bodies = 0;
+    int32_t *patched_bodies = nullptr;  // bodies split into patches
+    int32_t n_patched_units = 0;
+    int32_t *patched_units = nullptr;   // their units
+    double *Xstage = nullptr;     // [N][3] new positions of patched bodies
 
     double *bwd_dots = nullptr;   // [2E + 2F] family dot products (reverse step)
 
-    // bound reference (ip_plan_bind_reference): copies in the caller's element
-    // order for the element kernels, and packed records in a conflict-free
-    // order for the fused step
+    // bound reference (ip_plan_bind_reference): copies in the caller's
+    // element order (element kernels; source of the packed records)
     bool ref_bound = false;
     void *bref_l0 = nullptr, *bref_cs0 = nullptr, *bref_A0 = nullptr;  // real, caller order
     double *bref_V0 = nullptr;
     ip_reference bref{};
-    int32_t *edge_perm = nullptr;  // [E] packed position -> edge id (same body)
-    int32_t *face_perm = nullptr;  // [F] packed position -> face id (same body)
-    void *edge_rec = nullptr;      // [E] EdgeRec<real>
-    void *face_rec = nullptr;      // [F] FaceRec<real>
 
     size_t real_size() const { return prec == IP_F64 ? sizeof(double) : sizeof(float); }
 };
@@ -105,8 +127,27 @@ struct alignas(16) FaceRec {
 static_assert(sizeof(EdgeRec<double>) == 32 && sizeof(EdgeRec<float>) == 24, "edge record");
 static_assert(sizeof(FaceRec<double>) == 16 && sizeof(FaceRec<float>) == 16, "face record");
 
+// Work units of the fused step (workunits.hip).
+struct WorkUnitHost {
+    int32_t body = 0, owned = 0, n_nodes = 0;
+    int64_t node_begin = 0, node_end = 0, edge_begin = 0, edge_end = 0, face_begin = 0,
+            face_end = 0;
+};
+struct WorkUnits {
+    std::vector<WorkUnitHost> units;
+    std::vector<int32_t> nodes, edge_perm, face_perm;
+    std::vector<uint16_t> edge_lid, face_lid;
+};
+// Bodies of at most nmax_unit nodes and fmax_unit faces become one unit;
+// larger bodies are split into patches of at most patch_owned owned nodes
+// (further where a patch with its halo would not fit).  False if some body
+// cannot be split to fit.
+bool build_work_units(const ip_mesh *m, int nmax_unit, int fmax_unit, int patch_owned,
+                      WorkUnits &out);
+
 // launchers (k_forces.hip / k_transfer.hip); all asynchronous on `s`
-ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s);
+ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s,
+                          const int32_t *bodies = nullptr, int n_bodies = -1);
 ip_status launch_reference(ip_plan *p, const double *Xref, void *l0, void *cs0, void *A0,
                            hipStream_t s);
 ip_status launch_forces(ip_plan *p, const double *X, const ip_reference *ref,
@@ -132,9 +173,10 @@ ip_status launch_taylor(ip_plan *p, const double *X, const double *Dstar, double
 constexpr int kStepThreads = 768;
 constexpr int kStepNodesPerThread = 4;
 constexpr int kStepFacesPerThread = 8;   // faces held in registers per thread
+constexpr int kPatchOwned = 512;         // owned nodes per patch of a large body
 size_t step_fused_lds_bytes(int nmax, int tile_bytes);
 ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
-ip_status launch_pack_reference(ip_plan *p, hipStream_t s);
+ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s);
 ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
                             const ip_constants *k, const void *u, void *f, double dt,
                             double *V, double *A, hipStream_t s);

@@ -22,9 +22,9 @@ template <typename R>
 __global__ __launch_bounds__(kGeomThreads) void k_geometry(
     const double *__restrict__ X, const int32_t *__restrict__ faces,
     const int64_t *__restrict__ node_off, const int64_t *__restrict__ face_off,
-    double *__restrict__ V, double *__restrict__ A) {
+    double *__restrict__ V, double *__restrict__ A, const int32_t *__restrict__ bodies) {
     __shared__ double sh[kGeomThreads / 64];
-    const int b = blockIdx.x;
+    const int b = bodies ? bodies[blockIdx.x] : (int)blockIdx.x;
     if (face_off[b] == face_off[b + 1]) {   // no faces: the body may own no node
         if (threadIdx.x == 0) V[b] = A[b] = 0.0;
         return;
@@ -236,7 +236,7 @@ ip_status forces_impl(ip_plan *p, const double *X, const ip_reference *ref,
     double *Ab = A ? A : p->Abuf;
     if (p->B > 0)
         hipLaunchKernelGGL(k_geometry<R>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
-                           p->node_off, p->face_off, Vb, Ab);
+                           p->node_off, p->face_off, Vb, Ab, (const int32_t *)nullptr);
     if (p->E > 0)
         hipLaunchKernelGGL(k_edges<R>, dim3(nblocks(p->E, kElemThreads)), dim3(kElemThreads), 0,
                            s, X, (const int4 *)p->edges4, p->edge_off, p->B, p->E,
@@ -274,14 +274,16 @@ ip_status reference_impl(ip_plan *p, const double *X, void *l0, void *cs0, void 
 
 }  // namespace
 
-ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s) {
-    if (p->B == 0) return IP_OK;
+ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s,
+                          const int32_t *bodies, int n_bodies) {
+    const int nb = bodies ? n_bodies : p->B;
+    if (nb <= 0) return IP_OK;
     if (p->prec == IP_F64)
-        hipLaunchKernelGGL(k_geometry<double>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
-                           p->node_off, p->face_off, V, A);
+        hipLaunchKernelGGL(k_geometry<double>, dim3(nb), dim3(kGeomThreads), 0, s, X, p->faces,
+                           p->node_off, p->face_off, V, A, bodies);
     else
-        hipLaunchKernelGGL(k_geometry<float>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
-                           p->node_off, p->face_off, V, A);
+        hipLaunchKernelGGL(k_geometry<float>, dim3(nb), dim3(kGeomThreads), 0, s, X, p->faces,
+                           p->node_off, p->face_off, V, A, bodies);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }

@@ -38,11 +38,9 @@ constexpr int FK = kStepFacesPerThread;
 
 struct StepArgs {
     double *X;
-    const int32_t *faces;
-    const int4 *e4;
-    const int64_t *node_off, *edge_off, *face_off;
+    double *Xstage;          // new positions of patched bodies
+    const int64_t *node_off;
     const uint8_t *closed, *pinned;
-    const void *l0, *cs0, *A0;
     const double *V0, *ks, *kb, *kA, *kV, *mass;
     const void *u;
     void *f;
@@ -52,8 +50,10 @@ struct StepArgs {
     double dt;
     double *V, *A;
     uint32_t *status;
-    const void *erec, *frec; // packed records of the bound reference (packed variant)
-    const int32_t *bodies;   // body handled by each workgroup
+    // work units (one per workgroup, largest first)
+    const int32_t *wu_body, *wu_owned, *wu_nodes;
+    const int64_t *wu_noff, *wu_eoff, *wu_foff;
+    const void *erec, *frec; // packed element records
     int nmax;                // node capacity of the LDS layout
     int tile_bytes;          // bytes of the tile region
 };
@@ -81,18 +81,22 @@ __device__ __forceinline__ int cell_of(double x, double inv_h) {
     return (int)c;
 }
 
-__device__ __forceinline__ int block_min_int(int v, int *sh) {
+// Block-wide minimum / maximum of an int (every thread gets the result).
+template <bool MAX>
+__device__ __forceinline__ int block_extreme_int(int v, int *sh) {
+    const auto pick = [](int x, int y) { return MAX ? max(x, y) : min(x, y); };
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    for (int o = 32; o > 0; o >>= 1) v = pick(v, __shfl_xor(v, o, 64));
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    int r = INT_MAX;
-    for (int w = 0; w < NT / 64; ++w) r = min(r, sh[w]);
+    int r = sh[0];
+    for (int w = 1; w < NT / 64; ++w) r = pick(r, sh[w]);
     return r;
 }
 
-__device__ __forceinline__ int block_max_int(int v, int *sh) { return -block_min_int(-v, sh); }
+__device__ __forceinline__ int block_min_int(int v, int *sh) { return block_extreme_int<false>(v, sh); }
+__device__ __forceinline__ int block_max_int(int v, int *sh) { return block_extreme_int<true>(v, sh); }
 
 // In-place exclusive scan of a[0..n) by the whole block; returns the total.
 __device__ int block_exclusive_scan(int *a, int n, int *sh) {
@@ -280,7 +284,7 @@ struct RawEdge<float> {
 __device__ __forceinline__ double face_a0(const int4 &r, double) { return __hiloint2double(r.w, r.z); }
 __device__ __forceinline__ float face_a0(const int4 &r, float) { return __int_as_float(r.z); }
 
-template <typename R, bool PK>
+template <typename R>
 __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[NT / 64];
@@ -290,14 +294,19 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     __shared__ int cnt_bins[kCountBins + 1];
 
     const int tid = threadIdx.x;
-    const int b = a.bodies[blockIdx.x];
+    const int w = blockIdx.x;
+    const int b = a.wu_body[w];
+    const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
+    const bool whole = nl1 == nl0;                    // a whole body, nodes contiguous
     const int64_t n0 = a.node_off[b];
-    const int N = (int)(a.node_off[b + 1] - n0);
-    const int64_t e0 = a.edge_off[b];
-    const int E = (int)(a.edge_off[b + 1] - e0);
-    const int64_t f0 = a.face_off[b];
-    const int F = (int)(a.face_off[b + 1] - f0);
-    if (N == 0) {     // uniform over the block
+    const int NL = whole ? (int)(a.node_off[b + 1] - n0) : (int)(nl1 - nl0);   // unit nodes
+    const int N = whole ? NL : a.wu_owned[w];         // owned nodes (the first N)
+    const int32_t *gid = a.wu_nodes + nl0;            // patch: global node ids
+    const int64_t e0 = a.wu_eoff[2 * w];
+    const int E = (int)(a.wu_eoff[2 * w + 1] - e0);
+    const int64_t f0 = a.wu_foff[2 * w];
+    const int F = (int)(a.wu_foff[2 * w + 1] - f0);
+    if (NL == 0) {     // uniform over the block
         if (tid == 0) {
             a.V[b] = 0.0;
             a.A[b] = 0.0;
@@ -315,58 +324,42 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     uint16_t *occ_cnt = occ_start + a.nmax;                           // [nmax] node count
     bool bad = false;
 
-    // ---- faces of this thread, loaded first so that their latency overlaps
-    // the position copy; kept in registers for P1 and P2 ----
-    // Element order: in the packed variant the records are already in an
-    // order where each run of 64 touches distinct nodes, and lane t takes
-    // element t.  Otherwise lane l of every wave takes the contiguous strip
-    // [l S, (l+1) S) of the body's elements (S = ceil(count / 64)) and the
-    // waves step through it together, so the 64 lanes of one instruction
-    // touch elements S apart (elements in mesh order share nodes, up to 6
-    // lanes on one address).
-    const int lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = NT / 64;
-    const int Sf = (F + 63) >> 6;
+    // ---- faces of this thread (packed records: unit-local node ids and A0),
+    // loaded first so that their latency overlaps the position copy; kept in
+    // registers for P1 and P2.  The records are ordered so that each run of
+    // 64 touches distinct nodes, and lane t takes record t. ----
     int fi[FK][3];
     R fa0[FK];
     unsigned fmask = 0;
 #pragma unroll
     for (int s = 0; s < FK; ++s) {
-        int t;
-        bool ok;
-        if constexpr (PK) {
-            t = tid + s * NT;
-            ok = t < F;
-        } else {
-            const int q = wave + s * NW;
-            t = lane * Sf + q;
-            ok = q < Sf && t < F;
-        }
+        const int t = tid + s * NT;
         fi[s][0] = fi[s][1] = fi[s][2] = 0;
         fa0[s] = (R)1;
-        if (ok) {
+        if (t < F) {
             fmask |= 1u << s;
-            if constexpr (PK) {
-                const int4 r = ((const int4 *)a.frec)[f0 + t];
-                fi[s][0] = r.x & 0xFFFF;
-                fi[s][1] = (int)((unsigned)r.x >> 16);
-                fi[s][2] = r.y & 0xFFFF;
-                fa0[s] = face_a0(r, (R)0);
-            } else {
-                const int32_t *fb = a.faces + 3 * f0;
-                fi[s][0] = fb[3 * t] - (int)n0;
-                fi[s][1] = fb[3 * t + 1] - (int)n0;
-                fi[s][2] = fb[3 * t + 2] - (int)n0;
-                fa0[s] = ((const R *)a.A0)[f0 + t];
-            }
+            const int4 r = ((const int4 *)a.frec)[f0 + t];
+            fi[s][0] = r.x & 0xFFFF;
+            fi[s][1] = (int)((unsigned)r.x >> 16);
+            fi[s][2] = r.y & 0xFFFF;
+            fa0[s] = face_a0(r, (R)0);
         }
     }
 
-    // ---- P0: positions ----
-    const double *Xb = a.X + 3 * n0;
-    copy_to_lds(xs, Xb, 3 * N);
-    for (int i = tid; i < 3 * N; i += NT) Fs[i] = 0.0;
+    // ---- P0: positions (contiguous for a whole body, gathered for a patch) ----
+    if (whole) {
+        copy_to_lds(xs, a.X + 3 * n0, 3 * NL);
+    } else {
+        for (int i = tid; i < NL; i += NT) {
+            const int64_t g = gid[i];
+            xs[3 * i] = a.X[3 * g];
+            xs[3 * i + 1] = a.X[3 * g + 1];
+            xs[3 * i + 2] = a.X[3 * g + 2];
+        }
+    }
+    for (int i = tid; i < 3 * NL; i += NT) Fs[i] = 0.0;
     __syncthreads();
+    // cell bounding box of the owned nodes (the ones spread and interpolated)
     int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -387,28 +380,34 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
         kmax[c] = block_max_int(hi[c], ired);
     }
 
-    // ---- P1: volume and area ----
-    const vec3<double> anchor = ldx(xs, 0);
-    double v6 = 0.0, a2 = 0.0;
+    // ---- P1: volume and area (a whole body; a patched body's come from the
+    // geometry pass that precedes this kernel) ----
+    double Vb;
+    if (whole) {
+        const vec3<double> anchor = ldx(xs, 0);
+        double v6 = 0.0, a2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < FK; ++s) {
-        if (fmask & (1u << s)) {
-            double v, ar;
-            face_geometry<double, R>(ldx(xs, fi[s][0]), ldx(xs, fi[s][1]), ldx(xs, fi[s][2]),
-                                     anchor, v, ar);
-            v6 += v;
-            a2 += ar;
+        for (int s = 0; s < FK; ++s) {
+            if (fmask & (1u << s)) {
+                double v, ar;
+                face_geometry<double, R>(ldx(xs, fi[s][0]), ldx(xs, fi[s][1]), ldx(xs, fi[s][2]),
+                                         anchor, v, ar);
+                v6 += v;
+                a2 += ar;
+            }
         }
+        v6 = block_sum(v6, red);
+        a2 = block_sum(a2, red);
+        if (tid == 0) {
+            bcd[0] = v6 * (1.0 / 6.0);
+            a.V[b] = bcd[0];
+            a.A[b] = 0.5 * a2;
+        }
+        __syncthreads();
+        Vb = bcd[0];
+    } else {
+        Vb = a.V[b];
     }
-    v6 = block_sum(v6, red);
-    a2 = block_sum(a2, red);
-    if (tid == 0) {
-        bcd[0] = v6 * (1.0 / 6.0);
-        a.V[b] = bcd[0];
-        a.A[b] = 0.5 * a2;
-    }
-    __syncthreads();
-    const double Vb = bcd[0];
 
     // ---- P2: elements -> node accumulators ----
     {
@@ -426,106 +425,43 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
                 add3(Fs, k, gk);
             }
         }
-        const R *l0 = (const R *)a.l0 + e0;
-        const R *cs0 = (const R *)a.cs0 + 2 * e0;
-        const int4 *eb = a.e4 + e0;
         const double ks = a.ks[b], kb = a.kb[b];
-        if constexpr (PK) {
-            // packed records, two iterations ahead; the next edge's node
-            // positions are read before the current edge's accumulator
-            // additions are issued (waiting for them never waits for those)
-            using Raw = RawEdge<R>;
-            const auto fetch = [&](int t) {
-                Raw r{};
-                if (t < E) r = Raw::load(a.erec, (int)e0 + t);
-                return r;
-            };
-            const auto read_nodes = [&](const int4 &q, vec3<double> &y1, vec3<double> &y2,
-                                        vec3<double> &y3, vec3<double> &y4) {
-                const bool h = q.z != kNoNode && q.w != kNoNode;
-                y1 = ldx(xs, q.x);
-                y2 = ldx(xs, q.y);
-                y3 = ldx(xs, h ? q.z : 0);
-                y4 = ldx(xs, h ? q.w : 0);
-            };
-            Raw rc = fetch(tid), rn = fetch(tid + NT);
-            vec3<double> x1, x2, x3, x4;
-            if (tid < E) read_nodes(rc.ids(), x1, x2, x3, x4);
-            for (int t = tid; t < E; t += NT) {
-                const Raw cur = rc;
-                rc = rn;
-                rn = fetch(t + 2 * NT);
-                const int4 q = cur.ids();
-                const bool hinge = q.z != kNoNode && q.w != kNoNode;
-                vec3<R> f1, f2, f3, f4;
-                bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, cur.l0(), cur.c0(), cur.s0(),
-                                              ks, kb, f1, f2, f3, f4);
-                if (t + NT < E) read_nodes(rc.ids(), x1, x2, x3, x4);
-                add3(Fs, q.x, f1);
-                add3(Fs, q.y, f2);
-                if (hinge) {
-                    add3(Fs, q.z, f3);
-                    add3(Fs, q.w, f4);
-                }
-            }
-        } else {
-        // Edges in the same strip order as the faces.  Software pipeline:
-        // the next edge's node ids are loaded from memory two iterations
-        // ahead (its reference data one ahead), and its node positions are
-        // read from LDS before the current edge's accumulator additions are
-        // issued, so waiting for those reads never waits for the additions.
-        const int Se = (E + 63) >> 6;
-        const int ebase = lane * Se;
-        const auto edge_ids = [&](int qq) {
-            const int t = ebase + qq;
-            return qq < Se && t < E ? eb[t] : int4{(int)n0, (int)n0, -1, -1};
+        // edge records two iterations ahead; the next edge's node positions
+        // are read before the current edge's accumulator additions are issued
+        // (waiting for those reads never waits for the additions)
+        using Raw = RawEdge<R>;
+        const auto fetch = [&](int t) {
+            Raw r{};
+            if (t < E) r = Raw::load(a.erec, (int)e0 + t);
+            return r;
         };
         const auto read_nodes = [&](const int4 &q, vec3<double> &y1, vec3<double> &y2,
                                     vec3<double> &y3, vec3<double> &y4) {
-            const bool h = q.z >= 0 && q.w >= 0;
-            y1 = ldx(xs, q.x - (int)n0);
-            y2 = ldx(xs, q.y - (int)n0);
-            y3 = ldx(xs, h ? q.z - (int)n0 : 0);
-            y4 = ldx(xs, h ? q.w - (int)n0 : 0);
+            const bool h = q.z != kNoNode && q.w != kNoNode;
+            y1 = ldx(xs, q.x);
+            y2 = ldx(xs, q.y);
+            y3 = ldx(xs, h ? q.z : 0);
+            y4 = ldx(xs, h ? q.w : 0);
         };
-        int4 qc = edge_ids(wave), qn = edge_ids(wave + NW);
+        Raw rc = fetch(tid), rn = fetch(tid + NT);
         vec3<double> x1, x2, x3, x4;
-        read_nodes(qc, x1, x2, x3, x4);
-        R el0 = (R)1, c0 = (R)1, s0 = (R)0;
-        if (wave < Se && ebase + wave < E) {
-            el0 = l0[ebase + wave];
-            c0 = cs0[2 * (ebase + wave)];
-            s0 = cs0[2 * (ebase + wave) + 1];
-        }
-        for (int qe = wave; qe < Se; qe += NW) {
-            const bool live = ebase + qe < E;
-            const int4 q = qc;
-            qc = qn;
-            qn = edge_ids(qe + 2 * NW);
-            const R el0c = el0, c0c = c0, s0c = s0;
-            {
-                const int t = ebase + qe + NW;
-                if (qe + NW < Se && t < E) {
-                    el0 = l0[t];
-                    c0 = cs0[2 * t];
-                    s0 = cs0[2 * t + 1];
-                }
-            }
-            const bool hinge = q.z >= 0 && q.w >= 0;
+        if (tid < E) read_nodes(rc.ids(), x1, x2, x3, x4);
+        for (int t = tid; t < E; t += NT) {
+            const Raw cur = rc;
+            rc = rn;
+            rn = fetch(t + 2 * NT);
+            const int4 q = cur.ids();
+            const bool hinge = q.z != kNoNode && q.w != kNoNode;
             vec3<R> f1, f2, f3, f4;
-            if (live)
-                bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, el0c, c0c, s0c, ks, kb, f1,
-                                              f2, f3, f4);
-            if (qe + NW < Se) read_nodes(qc, x1, x2, x3, x4);
-            if (live) {
-                add3(Fs, q.x - (int)n0, f1);
-                add3(Fs, q.y - (int)n0, f2);
-                if (hinge) {
-                    add3(Fs, q.z - (int)n0, f3);
-                    add3(Fs, q.w - (int)n0, f4);
-                }
+            bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, cur.l0(), cur.c0(), cur.s0(), ks,
+                                          kb, f1, f2, f3, f4);
+            if (t + NT < E) read_nodes(rc.ids(), x1, x2, x3, x4);
+            add3(Fs, q.x, f1);
+            add3(Fs, q.y, f2);
+            if (hinge) {
+                add3(Fs, q.z, f3);
+                add3(Fs, q.w, f4);
             }
-        }
         }
     }
     __syncthreads();
@@ -534,7 +470,8 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     const int Cx = kmax[0] - kmin[0] + 1, Cy = kmax[1] - kmin[1] + 1, Cz = kmax[2] - kmin[2] + 1;
     const int Tx = Cx + 3, Ty = Cy + 3, Tz = Cz + 3;    // points kmin-1 .. kmax+2
     const long long Cl = (long long)Cx * Cy * Cz, Tl = (long long)Tx * Ty * Tz;
-    const bool use_tile = Cl <= 65535 && Cl * 8 <= a.tile_bytes && Tl * 8 <= a.tile_bytes;
+    const bool use_tile = Cx >= 1 && Cy >= 1 && Cz >= 1 && Cl <= 65535 && Cl * 8 <= a.tile_bytes &&
+                          Tl * 8 <= a.tile_bytes;
     const int C = use_tile ? (int)Cl : 0, T = use_tile ? (int)Tl : 0;
     int pos[K];
 #pragma unroll
@@ -730,86 +667,104 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
         if (use_tile) __syncthreads();
     }
     __syncthreads();
-    // back to node order (pinned nodes keep their position), staged in xs and
-    // written to memory once, coalesced
+    // back to node order (pinned nodes keep their position), staged in xs;
+    // a whole body is written in place, once and coalesced, a patch into the
+    // staging array (its nodes are other patches' halo until the step ends)
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         const int j = tid + s * NT;
         if (j < N) {
-            const bool pin = a.pinned[n0 + j] != 0;
+            const int64_t g = whole ? n0 + j : (int64_t)gid[j];
+            const bool pin = a.pinned[g] != 0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double v = pin ? Xb[3 * j + c] : Fs[3 * pos[s] + c];
-                xs[3 * j + c] = v;
-            }
+            for (int c = 0; c < 3; ++c) xs[3 * j + c] = pin ? a.X[3 * g + c] : Fs[3 * pos[s] + c];
         }
     }
     __syncthreads();
-    for (int i = tid; i < 3 * N; i += NT) a.X[3 * n0 + i] = xs[i];
+    if (whole) {
+        for (int i = tid; i < 3 * N; i += NT) a.X[3 * n0 + i] = xs[i];
+    } else {
+        for (int j = tid; j < N; j += NT) {
+            const int64_t g = gid[j];
+            a.Xstage[3 * g] = xs[3 * j];
+            a.Xstage[3 * g + 1] = xs[3 * j + 1];
+            a.Xstage[3 * g + 2] = xs[3 * j + 2];
+        }
+    }
     if (bad) atomicOr(a.status, IP_STATUS_DEGENERATE);
 }
 
-// Packed records of a bound reference, in the plan's conflict-free order.
+// Packed records (the fused step's element input): reference values of the
+// given reference gathered into the plan's record order, with the records'
+// unit-local node ids.
 template <typename R>
-__global__ void k_pack_edges(const int32_t *__restrict__ perm, const int4 *__restrict__ e4,
-                             const int64_t *__restrict__ edge_off,
-                             const int64_t *__restrict__ node_off, int B, int64_t E,
-                             const R *__restrict__ l0, const R *__restrict__ cs0,
+__global__ void k_pack_edges(const int32_t *__restrict__ perm, const ushort4 *__restrict__ lid,
+                             int64_t n, const R *__restrict__ l0, const R *__restrict__ cs0,
                              EdgeRec<R> *__restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= E) return;
-    const int e = perm[r];
-    const int64_t n0 = node_off[body_of(edge_off, B, r)];
-    const int4 q = e4[e];
+    if (r >= n) return;
+    const int64_t e = perm[r];
+    const ushort4 v = lid[r];
     EdgeRec<R> o{};
-    o.v[0] = (uint16_t)(q.x - n0);
-    o.v[1] = (uint16_t)(q.y - n0);
-    o.v[2] = q.z >= 0 ? (uint16_t)(q.z - n0) : kNoNode;
-    o.v[3] = q.w >= 0 ? (uint16_t)(q.w - n0) : kNoNode;
+    o.v[0] = v.x;
+    o.v[1] = v.y;
+    o.v[2] = v.z;
+    o.v[3] = v.w;
     o.l0 = l0[e];
-    o.c0 = cs0[2 * (int64_t)e];
-    o.s0 = cs0[2 * (int64_t)e + 1];
+    o.c0 = cs0[2 * e];
+    o.s0 = cs0[2 * e + 1];
     out[r] = o;
 }
 
 template <typename R>
-__global__ void k_pack_faces(const int32_t *__restrict__ perm, const int32_t *__restrict__ faces,
-                             const int64_t *__restrict__ face_off,
-                             const int64_t *__restrict__ node_off, int B, int64_t F,
-                             const R *__restrict__ A0, FaceRec<R> *__restrict__ out) {
+__global__ void k_pack_faces(const int32_t *__restrict__ perm, const ushort4 *__restrict__ lid,
+                             int64_t n, const R *__restrict__ A0, FaceRec<R> *__restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= F) return;
-    const int f = perm[r];
-    const int64_t n0 = node_off[body_of(face_off, B, r)];
+    if (r >= n) return;
+    const ushort4 v = lid[r];
     FaceRec<R> o{};
-    o.v[0] = (uint16_t)(faces[3 * (int64_t)f] - n0);
-    o.v[1] = (uint16_t)(faces[3 * (int64_t)f + 1] - n0);
-    o.v[2] = (uint16_t)(faces[3 * (int64_t)f + 2] - n0);
-    o.a0 = A0[f];
+    o.v[0] = v.x;
+    o.v[1] = v.y;
+    o.v[2] = v.z;
+    o.a0 = A0[perm[r]];
     out[r] = o;
 }
 
 template <typename R>
-void pack_reference(ip_plan *p, hipStream_t s) {
+void pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s) {
     const int t = 256;
-    if (p->E > 0)
-        hipLaunchKernelGGL(k_pack_edges<R>, dim3((unsigned)((p->E + t - 1) / t)), dim3(t), 0, s,
-                           p->edge_perm, (const int4 *)p->edges4, p->edge_off, p->node_off, p->B,
-                           p->E, (const R *)p->bref_l0, (const R *)p->bref_cs0,
-                           (EdgeRec<R> *)p->edge_rec);
-    if (p->F > 0)
-        hipLaunchKernelGGL(k_pack_faces<R>, dim3((unsigned)((p->F + t - 1) / t)), dim3(t), 0, s,
-                           p->face_perm, p->faces, p->face_off, p->node_off, p->B, p->F,
-                           (const R *)p->bref_A0, (FaceRec<R> *)p->face_rec);
+    if (p->n_erec > 0)
+        hipLaunchKernelGGL(k_pack_edges<R>, dim3((unsigned)((p->n_erec + t - 1) / t)), dim3(t), 0,
+                           s, p->erec_perm, (const ushort4 *)p->erec_lid, p->n_erec,
+                           (const R *)ref->l0, (const R *)ref->cs0, (EdgeRec<R> *)p->edge_rec);
+    if (p->n_frec > 0)
+        hipLaunchKernelGGL(k_pack_faces<R>, dim3((unsigned)((p->n_frec + t - 1) / t)), dim3(t), 0,
+                           s, p->frec_perm, (const ushort4 *)p->frec_lid, p->n_frec,
+                           (const R *)ref->A0, (FaceRec<R> *)p->face_rec);
+}
+
+// New positions of patched bodies: staging array -> X (owned nodes of each
+// patch unit; one workgroup per unit).
+__global__ void k_commit(const int32_t *__restrict__ units, const int64_t *__restrict__ noff,
+                         const int32_t *__restrict__ owned, const int32_t *__restrict__ nodes,
+                         const double *__restrict__ Xstage, double *__restrict__ X) {
+    const int w = units[blockIdx.x];
+    const int32_t *gid = nodes + noff[2 * w];
+    for (int j = threadIdx.x; j < owned[w]; j += blockDim.x) {
+        const int64_t g = gid[j];
+        X[3 * g] = Xstage[3 * g];
+        X[3 * g + 1] = Xstage[3 * g + 1];
+        X[3 * g + 2] = Xstage[3 * g + 2];
+    }
 }
 
 }  // namespace
 
-ip_status launch_pack_reference(ip_plan *p, hipStream_t s) {
+ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s) {
     if (p->prec == IP_F64)
-        pack_reference<double>(p, s);
+        pack_reference<double>(p, ref, s);
     else
-        pack_reference<float>(p, s);
+        pack_reference<float>(p, ref, s);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }
@@ -821,31 +776,23 @@ size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
 
 ip_status prepare_step_fused(ip_plan *p) {
     const int lds = (int)step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    const void *fn[2] = {p->prec == IP_F64 ? (const void *)k_step_fused<double, false>
-                                           : (const void *)k_step_fused<float, false>,
-                         p->prec == IP_F64 ? (const void *)k_step_fused<double, true>
-                                           : (const void *)k_step_fused<float, true>};
-    for (const void *f : fn)
-        IP_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    const void *fn = p->prec == IP_F64 ? (const void *)k_step_fused<double>
+                                       : (const void *)k_step_fused<float>;
+    IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return IP_OK;
 }
 
+// The records must hold `ref` (packed by the caller of this launcher).
 ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
                             const ip_constants *k, const void *u, void *f, double dt,
                             double *V, double *A, hipStream_t s) {
     if (p->B == 0) return IP_OK;
     StepArgs a{};
     a.X = X;
-    a.faces = p->faces;
-    a.e4 = (const int4 *)p->edges4;
+    a.Xstage = p->Xstage;
     a.node_off = p->node_off;
-    a.edge_off = p->edge_off;
-    a.face_off = p->face_off;
     a.closed = p->closed;
     a.pinned = p->pinned;
-    a.l0 = ref->l0;
-    a.cs0 = ref->cs0;
-    a.A0 = ref->A0;
     a.V0 = ref->V0;
     a.ks = k->ks;
     a.kb = k->kb;
@@ -865,25 +812,29 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
     a.V = V ? V : p->Vbuf;
     a.A = A ? A : p->Abuf;
     a.status = p->status;
-    a.bodies = p->fused_bodies;
-    a.nmax = p->fused_nmax;
-    a.tile_bytes = p->fused_tile_bytes;
-    // the bound reference is read from the packed records
-    const bool packed = ref == &p->bref && p->edge_rec != nullptr && p->face_rec != nullptr;
+    a.wu_body = p->wu_body;
+    a.wu_owned = p->wu_owned;
+    a.wu_nodes = p->wu_nodes;
+    a.wu_noff = p->wu_noff;
+    a.wu_eoff = p->wu_eoff;
+    a.wu_foff = p->wu_foff;
     a.erec = p->edge_rec;
     a.frec = p->face_rec;
+    a.nmax = p->fused_nmax;
+    a.tile_bytes = p->fused_tile_bytes;
+    // volume and area of patched bodies, before their patches need them
+    if (p->n_patched_bodies > 0)
+        IP_TRY(launch_geometry(p, X, a.V, a.A, s, p->patched_bodies, p->n_patched_bodies));
     const size_t lds = step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    if (p->prec == IP_F64) {
-        if (packed)
-            hipLaunchKernelGGL((k_step_fused<double, true>), dim3(p->n_fused), dim3(NT), lds, s, a);
-        else
-            hipLaunchKernelGGL((k_step_fused<double, false>), dim3(p->n_fused), dim3(NT), lds, s, a);
-    } else {
-        if (packed)
-            hipLaunchKernelGGL((k_step_fused<float, true>), dim3(p->n_fused), dim3(NT), lds, s, a);
-        else
-            hipLaunchKernelGGL((k_step_fused<float, false>), dim3(p->n_fused), dim3(NT), lds, s, a);
-    }
+    if (p->prec == IP_F64)
+        hipLaunchKernelGGL(k_step_fused<double>, dim3(p->n_units), dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_step_fused<float>, dim3(p->n_units), dim3(NT), lds, s, a);
     IP_HIP_CHECK(hipGetLastError());
+    if (p->n_patched_units > 0) {
+        hipLaunchKernelGGL(k_commit, dim3(p->n_patched_units), dim3(256), 0, s, p->patched_units,
+                           p->wu_noff, p->wu_owned, p->wu_nodes, p->Xstage, X);
+        IP_HIP_CHECK(hipGetLastError());
+    }
     return IP_OK;
 }

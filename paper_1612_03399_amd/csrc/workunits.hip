@@ -1,0 +1,266 @@
+// workunits.hip -- host-side construction of the fused step's work units.
+//
+// A work unit is what one workgroup of the fused step processes: a whole body
+// when its nodes, elements and LDS layout fit one workgroup, otherwise a patch
+// of a larger body.  A patch owns a compact set of the body's nodes (recursive
+// bisection of the mesh graph by breadth-first order from a peripheral node)
+// and carries every element that touches an owned node, plus the halo of the
+// non-owned nodes those elements reach; its forces are exact on the owned
+// nodes, which are the only ones it spreads, interpolates and moves.  The
+// element records of every unit use node ids local to the unit (owned nodes
+// first) and are ordered so that each run of 64 elements touches distinct
+// nodes where the mesh allows (the 64 lanes of one instruction then never add
+// into the same node accumulator).
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "ipibm_internal.h"
+
+namespace {
+
+// Greedy first fit of the elements into groups of 64 with pairwise distinct
+// nodes (local ids, -1 = none).
+void conflict_free_order(int count, int width, const int32_t *elem, int n_nodes,
+                         std::vector<std::vector<int32_t>> &node_groups,
+                         std::vector<int32_t> &order) {
+    constexpr int G = 64;
+    if ((int)node_groups.size() < n_nodes) node_groups.resize(n_nodes);
+    for (int v = 0; v < n_nodes; ++v) node_groups[v].clear();
+    std::vector<std::vector<int32_t>> groups;
+    size_t g0 = 0;
+    for (int e = 0; e < count; ++e) {
+        size_t g = g0;
+        for (;; ++g) {
+            if (g == groups.size()) groups.emplace_back();
+            if ((int)groups[g].size() >= G) continue;
+            bool clash = false;
+            for (int r = 0; r < width && !clash; ++r) {
+                const int v = elem[e * width + r];
+                if (v < 0) continue;
+                for (int32_t gg : node_groups[v])
+                    if ((size_t)gg == g) {
+                        clash = true;
+                        break;
+                    }
+            }
+            if (!clash) break;
+        }
+        groups[g].push_back(e);
+        for (int r = 0; r < width; ++r) {
+            const int v = elem[e * width + r];
+            if (v >= 0) node_groups[v].push_back((int32_t)g);
+        }
+        while (g0 < groups.size() && (int)groups[g0].size() >= G) ++g0;
+    }
+    order.clear();
+    for (auto &g : groups) order.insert(order.end(), g.begin(), g.end());
+}
+
+struct Builder {
+    const ip_mesh *m;
+    WorkUnits &out;
+    int nmax_unit, fmax_unit, patch_owned;
+    std::vector<std::vector<int32_t>> node_groups;
+    std::vector<int32_t> loc, order;
+
+    // Append one unit: `nodes` = global ids (owned first) or empty for a whole
+    // body; `edges`, `faces` = global element ids; `local` maps global node
+    // id - n0 to the unit's local id.
+    void emit(int b, bool whole, const std::vector<int32_t> &nodes, int owned,
+              const std::vector<int32_t> &edges, const std::vector<int32_t> &faces,
+              const std::vector<int32_t> &local, int64_t n0, int n_unit) {
+        WorkUnitHost u;
+        u.body = b;
+        u.owned = owned;
+        u.n_nodes = n_unit;
+        u.node_begin = (int64_t)out.nodes.size();
+        if (!whole) out.nodes.insert(out.nodes.end(), nodes.begin(), nodes.end());
+        u.node_end = (int64_t)out.nodes.size();
+        // edges
+        loc.resize(4 * edges.size());
+        for (size_t i = 0; i < edges.size(); ++i)
+            for (int r = 0; r < 4; ++r) {
+                const int32_t v = m->edges4[4 * (int64_t)edges[i] + r];
+                loc[4 * i + r] = v < 0 ? -1 : local[v - n0];
+            }
+        conflict_free_order((int)edges.size(), 4, loc.data(), n_unit, node_groups, order);
+        u.edge_begin = (int64_t)out.edge_perm.size();
+        for (int32_t i : order) {
+            out.edge_perm.push_back(edges[i]);
+            for (int r = 0; r < 4; ++r)
+                out.edge_lid.push_back(loc[4 * i + r] < 0 ? kNoNode : (uint16_t)loc[4 * i + r]);
+        }
+        u.edge_end = (int64_t)out.edge_perm.size();
+        // faces
+        loc.resize(3 * faces.size());
+        for (size_t i = 0; i < faces.size(); ++i)
+            for (int r = 0; r < 3; ++r) loc[3 * i + r] = local[m->faces[3 * (int64_t)faces[i] + r] - n0];
+        conflict_free_order((int)faces.size(), 3, loc.data(), n_unit, node_groups, order);
+        u.face_begin = (int64_t)out.face_perm.size();
+        for (int32_t i : order) {
+            out.face_perm.push_back(faces[i]);
+            for (int r = 0; r < 3; ++r) out.face_lid.push_back((uint16_t)loc[3 * i + r]);
+            out.face_lid.push_back(0);
+        }
+        u.face_end = (int64_t)out.face_perm.size();
+        out.units.push_back(u);
+    }
+
+    // Breadth-first order of the nodes of `part` (local body ids) from
+    // `seed`, over the body graph restricted to the part; nodes not reached
+    // (another component) follow in their given order.
+    void bfs_order(const std::vector<int32_t> &part, int seed, const std::vector<int32_t> &adj_ptr,
+                   const std::vector<int32_t> &adj, std::vector<int32_t> &mark, int stamp,
+                   std::vector<int32_t> &res) {
+        // mark[v] == stamp: in part, not visited; stamp + 1: visited
+        for (int v : part) mark[v] = stamp;
+        res.clear();
+        res.push_back(seed);
+        mark[seed] = stamp + 1;
+        for (size_t h = 0; h < res.size(); ++h) {
+            const int v = res[h];
+            for (int k = adj_ptr[v]; k < adj_ptr[v + 1]; ++k) {
+                const int w = adj[k];
+                if (mark[w] == stamp) {
+                    mark[w] = stamp + 1;
+                    res.push_back(w);
+                }
+            }
+        }
+        if (res.size() < part.size())
+            for (int v : part)
+                if (mark[v] == stamp) {
+                    mark[v] = stamp + 1;
+                    res.push_back(v);
+                }
+    }
+
+    bool build_body(int b) {
+        const int64_t n0 = m->node_off[b], n1 = m->node_off[b + 1];
+        const int64_t e0 = m->edge_off[b], e1 = m->edge_off[b + 1];
+        const int64_t f0 = m->face_off[b], f1 = m->face_off[b + 1];
+        const int n = (int)(n1 - n0);
+        std::vector<int32_t> edges(e1 - e0), faces(f1 - f0);
+        std::iota(edges.begin(), edges.end(), (int32_t)e0);
+        std::iota(faces.begin(), faces.end(), (int32_t)f0);
+        if (n <= nmax_unit && (f1 - f0) <= fmax_unit) {
+            std::vector<int32_t> local(n);
+            std::iota(local.begin(), local.end(), 0);
+            emit(b, true, {}, n, edges, faces, local, n0, n);
+            return true;
+        }
+        // mesh graph of the body (local ids) and node -> element incidence
+        std::vector<int32_t> deg(n + 1, 0);
+        for (int64_t f = f0; f < f1; ++f)
+            for (int r = 0; r < 3; ++r) deg[m->faces[3 * f + r] - n0] += 2;
+        std::vector<int32_t> adj_ptr(n + 1, 0);
+        for (int v = 0; v < n; ++v) adj_ptr[v + 1] = adj_ptr[v] + deg[v];
+        std::vector<int32_t> adj(adj_ptr[n]), fill(adj_ptr.begin(), adj_ptr.end() - 1);
+        for (int64_t f = f0; f < f1; ++f) {
+            const int i = m->faces[3 * f] - (int)n0, j = m->faces[3 * f + 1] - (int)n0,
+                      k = m->faces[3 * f + 2] - (int)n0;
+            adj[fill[i]++] = j; adj[fill[i]++] = k;
+            adj[fill[j]++] = k; adj[fill[j]++] = i;
+            adj[fill[k]++] = i; adj[fill[k]++] = j;
+        }
+        std::vector<std::vector<int32_t>> node_edges(n), node_faces(n);
+        for (int64_t e = e0; e < e1; ++e)
+            for (int r = 0; r < 4; ++r) {
+                const int32_t v = m->edges4[4 * e + r];
+                if (v >= 0) node_edges[v - n0].push_back((int32_t)e);
+            }
+        for (int64_t f = f0; f < f1; ++f)
+            for (int r = 0; r < 3; ++r) node_faces[m->faces[3 * f + r] - n0].push_back((int32_t)f);
+        // recursive bisection
+        std::vector<int32_t> mark(n, -1), ordr, emark_e(e1 - e0, -1), emark_f(f1 - f0, -1);
+        std::vector<int32_t> local(n, -1);
+        std::vector<std::vector<int32_t>> stack;
+        stack.emplace_back(n);
+        std::iota(stack.back().begin(), stack.back().end(), 0);
+        int stamp = 0, unit_stamp = 0;
+        while (!stack.empty()) {
+            std::vector<int32_t> part = std::move(stack.back());
+            stack.pop_back();
+            if ((int)part.size() > patch_owned) {
+                // split at half the breadth-first order from a peripheral node
+                bfs_order(part, part[0], adj_ptr, adj, mark, stamp, ordr);
+                stamp += 2;
+                const int far = ordr.back();
+                bfs_order(part, far, adj_ptr, adj, mark, stamp, ordr);
+                stamp += 2;
+                const size_t h = ordr.size() / 2;
+                stack.emplace_back(ordr.begin() + h, ordr.end());
+                stack.emplace_back(ordr.begin(), ordr.begin() + h);
+                continue;
+            }
+            // unit: owned nodes, elements touching them, halo
+            ++unit_stamp;
+            std::vector<int32_t> nodes, ue, uf;
+            for (size_t i = 0; i < part.size(); ++i) local[part[i]] = (int32_t)i;
+            for (int v : part) nodes.push_back((int32_t)(n0 + v));
+            const int owned = (int)part.size();
+            for (int v : part) {
+                for (int32_t e : node_edges[v])
+                    if (emark_e[e - e0] != unit_stamp) {
+                        emark_e[e - e0] = unit_stamp;
+                        ue.push_back(e);
+                    }
+                for (int32_t f : node_faces[v])
+                    if (emark_f[f - f0] != unit_stamp) {
+                        emark_f[f - f0] = unit_stamp;
+                        uf.push_back(f);
+                    }
+            }
+            const auto add_halo = [&](int32_t g) {
+                const int v = g - (int)n0;
+                if (local[v] < 0) {
+                    local[v] = (int32_t)nodes.size();
+                    nodes.push_back(g);
+                }
+            };
+            for (int32_t e : ue)
+                for (int r = 0; r < 4; ++r)
+                    if (m->edges4[4 * (int64_t)e + r] >= 0) add_halo(m->edges4[4 * (int64_t)e + r]);
+            for (int32_t f : uf)
+                for (int r = 0; r < 3; ++r) add_halo(m->faces[3 * (int64_t)f + r]);
+            const bool fits = (int)nodes.size() <= nmax_unit && (int)uf.size() <= fmax_unit;
+            if (!fits) {
+                for (int32_t g : nodes) local[g - n0] = -1;
+                if (owned <= 16) return false;       // cannot be made to fit
+                // split this part further
+                bfs_order(part, part[0], adj_ptr, adj, mark, stamp, ordr);
+                stamp += 2;
+                bfs_order(part, ordr.back(), adj_ptr, adj, mark, stamp, ordr);
+                stamp += 2;
+                const size_t h = ordr.size() / 2;
+                stack.emplace_back(ordr.begin() + h, ordr.end());
+                stack.emplace_back(ordr.begin(), ordr.begin() + h);
+                continue;
+            }
+            emit(b, false, nodes, owned, ue, uf, local, n0, (int)nodes.size());
+            for (int32_t g : nodes) local[g - n0] = -1;
+        }
+        return true;
+    }
+};
+
+}  // namespace
+
+bool build_work_units(const ip_mesh *m, int nmax_unit, int fmax_unit, int patch_owned,
+                      WorkUnits &out) {
+    out = WorkUnits{};
+    Builder bld{m, out, nmax_unit, fmax_unit, patch_owned, {}, {}, {}};
+    for (int b = 0; b < m->n_bodies; ++b)
+        if (!bld.build_body(b)) return false;
+    // largest units first (the tail of the launch runs the small ones)
+    std::vector<int32_t> idx(out.units.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        return out.units[x].n_nodes > out.units[y].n_nodes;
+    });
+    std::vector<WorkUnitHost> sorted;
+    for (int i : idx) sorted.push_back(out.units[i]);
+    out.units.swap(sorted);
+    return true;
+}

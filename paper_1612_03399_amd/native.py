@@ -183,10 +183,11 @@ class Plan:
         counts = (C.c_int64 * 4)()
         _check(LIB.ip_plan_sizes(h, counts))
         self.B, self.N, self.E, self.F = (int(c) for c in counts)
-        props = (C.c_int64 * 4)()
+        props = (C.c_int64 * 6)()
         _check(LIB.ip_plan_properties(h, props))
         self.fused = bool(props[0])
-        self.largest_body, self.tile_bytes, self.step_threads = (int(v) for v in props[1:])
+        (self.largest_unit, self.tile_bytes, self.step_threads, self.n_units,
+         self.patched_bodies) = (int(v) for v in props[1:])
 
     def close(self):
         if getattr(self, "handle", None):

@@ -38,6 +38,9 @@ CASES = {
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
                                          cells_per_unit=64),
+    # a 16 002-node shell: the fused step splits it into patches with halos
+    "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
+                                           cells_per_unit=96),
 }
 
 
@@ -242,3 +245,11 @@ def test_bound_reference_entry_points():
     N.ip_plan_bind_reference(plan, g2)
     F3 = host(N.ip_forces(plan, X, None, k))
     assert np.abs(F3).max() <= 1e-13 * np.abs(F1).max()
+
+
+def test_large_body_is_patched():
+    say("patches")
+    wl = CASES["ventricle_patched"]()
+    plan = N.Plan(wl, wl.grid, "f64")
+    assert plan.fused and plan.patched_bodies == 1
+    assert plan.n_units > wl.n_bodies
