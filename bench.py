@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 KERNEL_SOURCES = ["paper_1612_03399_amd/csrc/k_step.hip", "paper_1612_03399_amd/csrc/elements.h",
-                  "paper_1612_03399_amd/csrc/ipibm_internal.h"]
+                  "paper_1612_03399_amd/csrc/ipibm_internal.h",
+                  "paper_1612_03399_amd/csrc/workunits.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fused_{workload}_{dtype}.json")
 
 
@@ -73,9 +74,9 @@ def algorithmic_bytes(wl, touched, real_bytes):
     return nodes + edges + faces + bodies + grid
 
 
-def load_traffic(workload, dtype, nbytes_launch):
+def load_traffic(workload, dtype, options):
     """Measured HBM bytes per launch from the committed counter summary, when it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current kernel sources and launch shape (else None)."""
     path = TRAFFIC_FILE.format(workload=workload, dtype=dtype)
     if not os.path.exists(path):
         return None, None
@@ -83,7 +84,9 @@ def load_traffic(workload, dtype, nbytes_launch):
         t = json.load(fh)
     if t.get("source_hash") != kernel_source_hash():
         return None, "stale (kernel changed since the counters were taken)"
-    return t["bytes_per_launch"], path
+    if t.get("options", {}) != options:
+        return None, f"taken with launch options {t.get('options', {})}, not {options}"
+    return t["bytes_per_launch"], os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(wl, u, budget_s=20.0):
@@ -161,6 +164,91 @@ def backward_leg(N, W, bodies, dev, torch, log, steps=10, reps=3):
             "diff_bwd_over_fwd": b / f, "diff_loss": float(loss.item())}
 
 
+def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
+    """The uneven batch (4096 bodies of levels 2-5, 512^3, FP32 forces and
+    grid): the batched step (one fused launch over all work units), the same
+    captured in a hipGraph and replayed, and plain per-body launches (one plan
+    and one ip_step per body) against the batched step on a seeded sample of
+    the bodies.  The velocity is a seeded uniform random field generated on
+    the device: the cost does not depend on its values."""
+    wl = W.config2()
+    log(f"uneven leg: {wl.n_bodies} bodies, {wl.n_nodes} nodes")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1002)
+    u = (torch.rand((3, wl.grid.nz, wl.grid.ny, wl.grid.nx), generator=g, device=dev,
+                    dtype=torch.float32) - 0.5) * 0.2
+    f = torch.zeros_like(u)
+    k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
+    plan = N.Plan(wl, wl.grid, "f32")
+    N.ip_plan_bind_reference(plan, N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev)))
+    X = torch.as_tensor(wl.X).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    batched = timed(lambda: N.ip_step(plan, X, None, k, u, f, wl.dt, stream=stream), steps)
+    gr = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(stream)
+    with torch.cuda.stream(s2):
+        N.ip_step(plan, X, None, k, u, f, wl.dt, stream=s2)
+    stream.wait_stream(s2)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(gr):
+        for _ in range(10):
+            N.ip_step(plan, X, None, k, u, f, wl.dt, stream=torch.cuda.current_stream())
+    graph = timed(gr.replay, 3) / 10
+    code, flags = N.ip_plan_status(plan)
+    if code != N.IP_OK:
+        raise SystemExit(f"device status {code} flags {flags} in the uneven leg")
+    out = {"uneven_workload": wl.name, "uneven_nodes": wl.n_nodes,
+           "uneven_units": plan.n_units, "uneven_patched_bodies": plan.patched_bodies,
+           "uneven_batched_ms": batched, "uneven_graph_ms": graph,
+           "uneven_node_steps_per_s": wl.n_nodes / (graph * 1e-3)}
+    del gr, plan
+    # per-body launches on a sample, against the batched step of the same bodies
+    ids = np.sort(np.random.default_rng(7).choice(wl.n_bodies, sample, replace=False))
+    sub = W.subset(wl, ids)
+    ks = N.Constants.from_arrays(sub.ks, sub.kb, sub.kA, sub.kV, sub.mass, dev)
+    bplan = N.Plan(sub, sub.grid, "f32")
+    N.ip_plan_bind_reference(bplan, N.ip_reference_from(bplan, torch.as_tensor(sub.Xref).to(dev)))
+    Xs = torch.as_tensor(sub.X).to(dev)
+    sample_batched = timed(lambda: N.ip_step(bplan, Xs, None, ks, u, f, wl.dt, stream=stream), steps)
+    singles = []
+    for b in ids:
+        one = W.subset(wl, [b])
+        p1 = N.Plan(one, one.grid, "f32")
+        N.ip_plan_bind_reference(p1, N.ip_reference_from(p1, torch.as_tensor(one.Xref).to(dev)))
+        singles.append((p1, torch.as_tensor(one.X).to(dev),
+                        N.Constants.from_arrays(one.ks, one.kb, one.kA, one.kV, one.mass, dev)))
+
+    def per_body():
+        for p1, x1, k1 in singles:
+            N.ip_step(p1, x1, None, k1, u, f, wl.dt, stream=stream)
+
+    sample_single = timed(per_body, 3)
+    for p1, _, _ in singles:
+        code, flags = N.ip_plan_status(p1)
+        if code != N.IP_OK:
+            raise SystemExit(f"device status {code} flags {flags} in a per-body plan")
+    out.update({"per_body_sample": int(sample), "per_body_sample_nodes": sub.n_nodes,
+                "per_body_sample_ms": sample_single, "batched_sample_ms": sample_batched,
+                "per_body_over_batched": sample_single / sample_batched})
+    log(f"uneven: batched {batched:.3f} ms, graph {graph:.3f} ms/step; sample of {sample}: "
+        f"per-body {sample_single:.3f} ms vs batched {sample_batched:.3f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,8 +256,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--bodies", type=int, default=1000)
+    ap.add_argument("--options", default=None,
+                    help="launch options as JSON (skips the autotuner), e.g. '{\"threads\": 384}'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and graph legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other-precision, graph, differentiation and uneven legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -180,6 +271,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1612_03399_amd import autotune as AT
     from paper_1612_03399_amd import native as N
     from paper_1612_03399_amd import workload as W
 
@@ -198,34 +290,55 @@ def main():
     log(f"workload {wl.name}: {wl.n_nodes} nodes, {wl.n_edges} edges, {wl.n_faces} faces")
     u_host = wl.velocity(dtype=np.float64)
     stream = torch.cuda.current_stream()
+    k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
+    X0 = torch.as_tensor(wl.X).to(dev)
+
+    # launch shape: autotuned on this batch (untimed set-up) unless given
+    tuning = None
+    if args.options is not None:
+        options = json.loads(args.options)
+    else:
+        rdt = N.real_dtype(args.precision)
+        probe = N.Plan(wl, wl.grid, args.precision)
+        ref0 = N.ip_reference_from(probe, torch.as_tensor(wl.Xref).to(dev))
+        options, tuning = AT.autotune(wl, wl.grid, args.precision, X0, ref0, k,
+                                      torch.as_tensor(u_host).to(dev, rdt), wl.dt)
+        probe.close()
+        for r in tuning:
+            log(f"  options {r['options']}: {r['ms']:.4f} ms ({r['units']} units, "
+                f"{r['threads']} threads, tile {r['tile_bytes']} B)")
+        log(f"autotuned options: {options}")
 
     def setup(precision):
         rdt = N.real_dtype(precision)
         u = torch.as_tensor(u_host).to(dev, rdt)
-        plan = N.Plan(wl, wl.grid, precision)
+        plan = N.Plan(wl, wl.grid, precision, options)
         # the reference is bound once (packed element records); steps pass None
         N.ip_plan_bind_reference(plan, N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev)))
-        ref = None
-        k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
-        X = torch.as_tensor(wl.X).to(dev)
+        X = X0.clone()
         f = torch.zeros(u.shape, dtype=rdt, device=dev)
         V = torch.empty(wl.n_bodies, dtype=torch.float64, device=dev)
         A = torch.empty_like(V)
-        return plan, ref, k, X, u, f, V, A
+        return plan, None, k, X, u, f, V, A
 
     plan, ref, k, X, u, f, V, A = setup(args.precision)
     ms = time_steps(N, plan, X, ref, k, u, f, wl.dt, V, A, args.steps, args.warmup, stream, torch)
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags}")
-    log(f"timed {args.steps} steps: {ms:.4f} ms/step (fused path: {plan.fused})")
+    log(f"timed {args.steps} steps: {ms:.4f} ms/step (fused path: {plan.fused}, "
+        f"{plan.n_units} units, {plan.step_threads} threads)")
 
     real_bytes = 8 if args.precision == "f64" else 4
     touched = touched_points(wl.X, wl.grid)
     bytes_step = algorithmic_bytes(wl, touched, real_bytes)
     gbs = bytes_step / (ms * 1e-3) / 1e9
     value = wl.n_nodes / (ms * 1e-3)
-    traffic, traffic_src = load_traffic(wl.name, args.precision, bytes_step)
+    traffic, traffic_src = load_traffic(wl.name, args.precision, options)
+    kernel = (f"k_step_fused<{'double' if args.precision == 'f64' else 'float'}, "
+              f"{plan.step_threads}>") if plan.fused else "unfused step"
+    if plan.patched_bodies:
+        kernel += " + geometry and commit passes"
 
     out = {
         "metric": "Lagrangian node-steps/s (forces+interp+spread+update)",
@@ -235,16 +348,21 @@ def main():
         "data": "synthetic (seeded icosphere drops, random-Fourier MAC velocity)",
         "config": {"workload": wl.name, "bodies": wl.n_bodies, "nodes": wl.n_nodes,
                    "edges": wl.n_edges, "faces": wl.n_faces,
-                   "grid": [wl.grid.nx, wl.grid.ny, wl.grid.nz], "dt": wl.dt},
+                   "grid": [wl.grid.nx, wl.grid.ny, wl.grid.nz], "dt": wl.dt,
+                   "launch_options": options, "work_units": plan.n_units,
+                   "threads": plan.step_threads},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step_fused" if plan.fused else "unfused step",
+                     "kernel": kernel,
                      "algorithmic_bytes_per_launch": bytes_step,
                      "bytes_per_node": bytes_step / wl.n_nodes,
                      "touched_grid_points": touched,
                      "traffic_source": traffic_src},
     }
-    del plan, ref, k, X, u, f
+    if tuning is not None:
+        out["autotune"] = [{"options": r["options"], "ms": r["ms"], "units": r["units"],
+                            "threads": r["threads"]} for r in tuning]
+    del plan, X, u, f
     torch.cuda.empty_cache()
 
     if not args.no_extras:
@@ -280,11 +398,13 @@ def main():
         torch.cuda.synchronize()
         extras[f"{other}_graph_ms_per_step"] = e0.elapsed_time(e1) / (10 * reps)
         log(f"{other} graph replay: {extras[f'{other}_graph_ms_per_step']:.4f} ms/step")
+        del g, plan2, X2, u2, f2
+        torch.cuda.empty_cache()
+        if args.precision == "f64":
+            extras.update(backward_leg(N, W, args.bodies, dev, torch, log))
+        torch.cuda.empty_cache()
+        extras.update(uneven_leg(N, W, dev, torch, log))
         out["extras"] = extras
-        del g, plan2
-
-    if not args.no_extras and args.precision == "f64":
-        out.setdefault("extras", {}).update(backward_leg(N, W, args.bodies, dev, torch, log))
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -114,11 +114,35 @@ typedef struct {
     const double *mass;
 } ip_constants;
 
+/* Launch-shape options of the fused step (0 in a field = the default):
+ *   unit_nodes  bodies of at most this many nodes are one work unit (default
+ *               and maximum: 4 x threads); larger bodies are split into
+ *               patches;
+ *   patch_owned owned nodes per patch (default 512, at least 16);
+ *   tile_bytes  cap on the LDS tile region of a workgroup (default: all LDS
+ *               left once the largest unit's arrays are placed; at least
+ *               4096);
+ *   threads     threads per workgroup of the fused kernel: 768 (default) or
+ *               384, with units of at most 4 x threads nodes.  At 384
+ *               threads, small units and a capped tile let two workgroups
+ *               share a compute unit.
+ * The choice changes the speed, not the results beyond summation order. */
+typedef struct {
+    int32_t unit_nodes;
+    int32_t patch_owned;
+    int32_t tile_bytes;
+    int32_t threads;
+} ip_plan_options;
+
 /* Build a plan: validates and copies the mesh, builds the node gather lists
  * and allocates workspace for N nodes.  `grid` may be NULL for plans that only
  * compute forces.  On success *plan is set; on failure it is left NULL. */
 ip_status ip_plan_create(ip_plan **plan, const ip_mesh *mesh, const ip_grid *grid,
                          ip_precision precision);
+
+/* ip_plan_create with launch-shape options (`options` may be NULL). */
+ip_status ip_plan_create_ex(ip_plan **plan, const ip_mesh *mesh, const ip_grid *grid,
+                            ip_precision precision, const ip_plan_options *options);
 
 /* Release every resource of the plan (synchronizes the device). NULL is ok. */
 ip_status ip_plan_destroy(ip_plan *plan);

@@ -66,7 +66,8 @@ void free_plan(ip_plan *p) {
     delete p;
 }
 
-ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_precision prec) {
+ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_precision prec,
+                     const ip_plan_options &opt) {
     const int B = m->n_bodies;
     if (B < 0) return arg_error("n_bodies < 0");
     if (prec != IP_F64 && prec != IP_F32) return arg_error("unknown precision");
@@ -167,16 +168,20 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
                                        p->device));
     if (lds_optin <= 0) IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin,
                                      hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
-    const int unit_nodes = kStepThreads * kStepNodesPerThread;
-    const int unit_faces = kStepThreads * kStepFacesPerThread;
+    p->step_threads = opt.threads > 0 ? opt.threads : kStepThreads;
+    const int unit_max = p->step_threads * kStepNodesPerThread;
+    const int unit_nodes = opt.unit_nodes > 0 ? std::min(opt.unit_nodes, unit_max) : unit_max;
+    const int unit_faces = p->step_threads * kStepFacesPerThread;
+    const int patch_owned = opt.patch_owned > 0 ? opt.patch_owned : kPatchOwned;
     WorkUnits wu;
-    if (B > 0 && build_work_units(m, unit_nodes, unit_faces, kPatchOwned, wu)) {
+    if (B > 0 && build_work_units(m, unit_nodes, unit_max, unit_faces, patch_owned, wu)) {
         int nmax = 1;
         for (const auto &u : wu.units) nmax = std::max(nmax, u.n_nodes);
         // LDS left for the grid tile once positions, accumulators and the
         // cell list are placed (1 KB kept for the kernel's static LDS)
-        const long long tile_bytes =
+        long long tile_bytes =
             ((long long)lds_optin - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
+        if (opt.tile_bytes > 0) tile_bytes = std::min<long long>(tile_bytes, opt.tile_bytes / 16 * 16);
         if (tile_bytes >= 4096) {
             p->fused_all = true;
             p->fused_nmax = nmax;
@@ -269,11 +274,25 @@ const char *ip_last_error(void) { return g_last_error.c_str(); }
 
 ip_status ip_plan_create(ip_plan **plan, const ip_mesh *mesh, const ip_grid *grid,
                          ip_precision precision) {
+    return ip_plan_create_ex(plan, mesh, grid, precision, nullptr);
+}
+
+ip_status ip_plan_create_ex(ip_plan **plan, const ip_mesh *mesh, const ip_grid *grid,
+                            ip_precision precision, const ip_plan_options *options) {
     if (!plan) return arg_error("plan out-pointer is NULL");
     *plan = nullptr;
     if (!mesh) return arg_error("mesh is NULL");
+    ip_plan_options opt{};
+    if (options) {
+        opt = *options;
+        if (opt.unit_nodes < 0 || opt.patch_owned < 0 || opt.tile_bytes < 0 ||
+            (opt.patch_owned > 0 && opt.patch_owned < 16) ||
+            (opt.tile_bytes > 0 && opt.tile_bytes < 4096) ||
+            (opt.threads != 0 && opt.threads != 384 && opt.threads != 768))
+            return arg_error("invalid plan options");
+    }
     ip_plan *p = new ip_plan();
-    ip_status st = build_plan(p, mesh, grid, precision);
+    ip_status st = build_plan(p, mesh, grid, precision, opt);
     if (st != IP_OK) {
         free_plan(p);
         return st;
@@ -303,7 +322,7 @@ ip_status ip_plan_properties(const ip_plan *plan, int64_t props[6]) {
     props[0] = plan->fused_all ? 1 : 0;
     props[1] = plan->fused_nmax;
     props[2] = plan->fused_tile_bytes;
-    props[3] = kStepThreads;
+    props[3] = plan->step_threads;
     props[4] = plan->n_units;
     props[5] = plan->n_patched_bodies;
     return IP_OK;

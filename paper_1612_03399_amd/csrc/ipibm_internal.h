@@ -69,6 +69,7 @@ struct ip_plan {
     bool fused_all = false;
     int fused_nmax = 0;           // largest work unit (nodes, owned + halo)
     int fused_tile_bytes = 0;     // LDS bytes for the per-unit grid tile
+    int step_threads = 768;       // threads per workgroup of the fused step (768 or 384)
     int32_t n_units = 0;
     int32_t *wu_body = nullptr;   // [n_units] body of each unit, largest unit first
     int32_t *wu_owned = nullptr;  // [n_units] owned nodes
@@ -138,12 +139,12 @@ struct WorkUnits {
     std::vector<int32_t> nodes, edge_perm, face_perm;
     std::vector<uint16_t> edge_lid, face_lid;
 };
-// Bodies of at most nmax_unit nodes and fmax_unit faces become one unit;
+// Bodies of at most whole_max nodes and fmax_unit faces become one unit;
 // larger bodies are split into patches of at most patch_owned owned nodes
-// (further where a patch with its halo would not fit).  False if some body
-// cannot be split to fit.
-bool build_work_units(const ip_mesh *m, int nmax_unit, int fmax_unit, int patch_owned,
-                      WorkUnits &out);
+// (further where a patch with its halo would exceed nmax_unit nodes or
+// fmax_unit faces).  False if some body cannot be split to fit.
+bool build_work_units(const ip_mesh *m, int whole_max, int nmax_unit, int fmax_unit,
+                      int patch_owned, WorkUnits &out);
 
 // launchers (k_forces.hip / k_transfer.hip); all asynchronous on `s`
 ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s,
@@ -170,7 +171,7 @@ ip_status launch_taylor(ip_plan *p, const double *X, const double *Dstar, double
                         double *gX, hipStream_t s);
 
 // fused step (k_step.hip)
-constexpr int kStepThreads = 768;
+constexpr int kStepThreads = 768;         // default threads per workgroup (also 384)
 constexpr int kStepNodesPerThread = 4;
 constexpr int kStepFacesPerThread = 8;   // faces held in registers per thread
 constexpr int kPatchOwned = 512;         // owned nodes per patch of a large body

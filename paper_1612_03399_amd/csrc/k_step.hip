@@ -31,7 +31,6 @@
 
 namespace {
 
-constexpr int NT = kStepThreads;
 constexpr int K = kStepNodesPerThread;
 constexpr int kCountBins = 32;     // occupied cells are ordered by node count (capped)
 constexpr int FK = kStepFacesPerThread;
@@ -82,7 +81,7 @@ __device__ __forceinline__ int cell_of(double x, double inv_h) {
 }
 
 // Block-wide minimum / maximum of an int (every thread gets the result).
-template <bool MAX>
+template <int NT, bool MAX>
 __device__ __forceinline__ int block_extreme_int(int v, int *sh) {
     const auto pick = [](int x, int y) { return MAX ? max(x, y) : min(x, y); };
 #pragma unroll
@@ -95,10 +94,13 @@ __device__ __forceinline__ int block_extreme_int(int v, int *sh) {
     return r;
 }
 
-__device__ __forceinline__ int block_min_int(int v, int *sh) { return block_extreme_int<false>(v, sh); }
-__device__ __forceinline__ int block_max_int(int v, int *sh) { return block_extreme_int<true>(v, sh); }
+template <int NT>
+__device__ __forceinline__ int block_min_int(int v, int *sh) { return block_extreme_int<NT, false>(v, sh); }
+template <int NT>
+__device__ __forceinline__ int block_max_int(int v, int *sh) { return block_extreme_int<NT, true>(v, sh); }
 
 // In-place exclusive scan of a[0..n) by the whole block; returns the total.
+template <int NT>
 __device__ int block_exclusive_scan(int *a, int n, int *sh) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int chunk = (n + NT - 1) / NT;
@@ -130,7 +132,7 @@ __device__ int block_exclusive_scan(int *a, int n, int *sh) {
 }
 
 // Copy n values from global memory to LDS, U loads in flight per thread.
-template <typename T, int U = 8>
+template <int NT, typename T, int U = 8>
 __device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__restrict__ src, int n) {
     for (int base = 0; base < n; base += NT * U) {
         T v[U];
@@ -160,7 +162,7 @@ struct TileGeom {
 };
 
 // Stage the tile of one grid field into LDS, U loads in flight per thread.
-template <typename R, int U = 8>
+template <int NT, typename R, int U = 8>
 __device__ __forceinline__ void stage_tile(R *__restrict__ tile, const R *__restrict__ field,
                                            const TileGeom &g) {
     for (int base = 0; base < g.T; base += NT * U) {
@@ -284,7 +286,7 @@ struct RawEdge<float> {
 __device__ __forceinline__ double face_a0(const int4 &r, double) { return __hiloint2double(r.w, r.z); }
 __device__ __forceinline__ float face_a0(const int4 &r, float) { return __int_as_float(r.z); }
 
-template <typename R>
+template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[NT / 64];
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
 
     // ---- P0: positions (contiguous for a whole body, gathered for a patch) ----
     if (whole) {
-        copy_to_lds(xs, a.X + 3 * n0, 3 * NL);
+        copy_to_lds<NT>(xs, a.X + 3 * n0, 3 * NL);
     } else {
         for (int i = tid; i < NL; i += NT) {
             const int64_t g = gid[i];
@@ -376,8 +378,8 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     int kmin[3], kmax[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        kmin[c] = block_min_int(lo[c], ired);
-        kmax[c] = block_max_int(hi[c], ired);
+        kmin[c] = block_min_int<NT>(lo[c], ired);
+        kmax[c] = block_max_int<NT>(hi[c], ired);
     }
 
     // ---- P1: volume and area (a whole body; a patched body's come from the
@@ -495,8 +497,8 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
         int *occ_idx = hist + C;
         for (int c = tid; c < C; c += NT) occ_idx[c] = hist[c] > 0 ? 1 : 0;
         __syncthreads();
-        const int n_occ = block_exclusive_scan(occ_idx, C, ired);
-        block_exclusive_scan(hist, C, ired);
+        const int n_occ = block_exclusive_scan<NT>(occ_idx, C, ired);
+        block_exclusive_scan<NT>(hist, C, ired);
         for (int c = tid; c < C; c += NT) {
             const int start = hist[c];
             const int next = c + 1 < C ? hist[c + 1] : N;
@@ -625,7 +627,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     for (int d = 0; d < 3; ++d) {
         const R *ud = (const R *)a.u + d * a.field;
         if (use_tile) {
-            stage_tile(utile, ud, tg);
+            stage_tile<NT>(utile, ud, tg);
             __syncthreads();
         }
         for (int p = tid; p < N; p += NT) {
@@ -774,10 +776,15 @@ size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
     return (size_t)nmax * 48 + (size_t)tile_bytes + (size_t)nmax * 2 * sizeof(uint16_t);
 }
 
+template <typename R>
+const void *step_kernel(int threads) {
+    return threads == 384 ? (const void *)k_step_fused<R, 384> : (const void *)k_step_fused<R, 768>;
+}
+
 ip_status prepare_step_fused(ip_plan *p) {
     const int lds = (int)step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    const void *fn = p->prec == IP_F64 ? (const void *)k_step_fused<double>
-                                       : (const void *)k_step_fused<float>;
+    const void *fn = p->prec == IP_F64 ? step_kernel<double>(p->step_threads)
+                                       : step_kernel<float>(p->step_threads);
     IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return IP_OK;
 }
@@ -826,10 +833,18 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
     if (p->n_patched_bodies > 0)
         IP_TRY(launch_geometry(p, X, a.V, a.A, s, p->patched_bodies, p->n_patched_bodies));
     const size_t lds = step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    if (p->prec == IP_F64)
-        hipLaunchKernelGGL(k_step_fused<double>, dim3(p->n_units), dim3(NT), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_step_fused<float>, dim3(p->n_units), dim3(NT), lds, s, a);
+    const int nt = p->step_threads;
+    if (p->prec == IP_F64) {
+        if (nt == 384)
+            hipLaunchKernelGGL((k_step_fused<double, 384>), dim3(p->n_units), dim3(nt), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_step_fused<double, 768>), dim3(p->n_units), dim3(nt), lds, s, a);
+    } else {
+        if (nt == 384)
+            hipLaunchKernelGGL((k_step_fused<float, 384>), dim3(p->n_units), dim3(nt), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_step_fused<float, 768>), dim3(p->n_units), dim3(nt), lds, s, a);
+    }
     IP_HIP_CHECK(hipGetLastError());
     if (p->n_patched_units > 0) {
         hipLaunchKernelGGL(k_commit, dim3(p->n_patched_units), dim3(256), 0, s, p->patched_units,

@@ -60,7 +60,7 @@ void conflict_free_order(int count, int width, const int32_t *elem, int n_nodes,
 struct Builder {
     const ip_mesh *m;
     WorkUnits &out;
-    int nmax_unit, fmax_unit, patch_owned;
+    int whole_max, nmax_unit, fmax_unit, patch_owned;
     std::vector<std::vector<int32_t>> node_groups;
     std::vector<int32_t> loc, order;
 
@@ -144,7 +144,7 @@ struct Builder {
         std::vector<int32_t> edges(e1 - e0), faces(f1 - f0);
         std::iota(edges.begin(), edges.end(), (int32_t)e0);
         std::iota(faces.begin(), faces.end(), (int32_t)f0);
-        if (n <= nmax_unit && (f1 - f0) <= fmax_unit) {
+        if (n <= whole_max && (f1 - f0) <= fmax_unit) {
             std::vector<int32_t> local(n);
             std::iota(local.begin(), local.end(), 0);
             emit(b, true, {}, n, edges, faces, local, n0, n);
@@ -247,10 +247,10 @@ struct Builder {
 
 }  // namespace
 
-bool build_work_units(const ip_mesh *m, int nmax_unit, int fmax_unit, int patch_owned,
-                      WorkUnits &out) {
+bool build_work_units(const ip_mesh *m, int whole_max, int nmax_unit, int fmax_unit,
+                      int patch_owned, WorkUnits &out) {
     out = WorkUnits{};
-    Builder bld{m, out, nmax_unit, fmax_unit, patch_owned, {}, {}, {}};
+    Builder bld{m, out, whole_max, nmax_unit, fmax_unit, patch_owned, {}, {}, {}};
     for (int b = 0; b < m->n_bodies; ++b)
         if (!bld.build_body(b)) return false;
     // largest units first (the tail of the launch runs the small ones)

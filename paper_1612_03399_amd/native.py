@@ -41,6 +41,11 @@ class ip_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double)]
 
 
+class ip_plan_options(C.Structure):
+    _fields_ = [("unit_nodes", C.c_int32), ("patch_owned", C.c_int32), ("tile_bytes", C.c_int32),
+                ("threads", C.c_int32)]
+
+
 class ip_reference(C.Structure):
     _fields_ = [("l0", C.c_void_p), ("cs0", C.c_void_p), ("A0", C.c_void_p),
                 ("V0", C.c_void_p)]
@@ -58,6 +63,8 @@ def _load():
     vp, i32, d = C.c_void_p, C.c_int32, C.c_double
     sig = {
         "ip_plan_create": [C.POINTER(vp), C.POINTER(ip_mesh), C.POINTER(ip_grid), i32],
+        "ip_plan_create_ex": [C.POINTER(vp), C.POINTER(ip_mesh), C.POINTER(ip_grid), i32,
+                              C.POINTER(ip_plan_options)],
         "ip_plan_destroy": [vp],
         "ip_plan_sizes": [vp, C.POINTER(C.c_int64)],
         "ip_plan_properties": [vp, C.POINTER(C.c_int64)],
@@ -156,7 +163,7 @@ class Plan:
     """Owns an ``ip_plan``.  ``mesh`` is any object with host arrays node_off,
     edge_off, face_off, faces, edges4, closed, pinned (see ip_mesh)."""
 
-    def __init__(self, mesh, grid=None, precision: str = "f64"):
+    def __init__(self, mesh, grid=None, precision: str = "f64", options=None):
         self.precision = precision
         self.dtype = real_dtype(precision)
         self._keep = [np.ascontiguousarray(mesh.node_off, np.int64),
@@ -177,8 +184,13 @@ class Plan:
         else:
             self.grid = None
         h = C.c_void_p()
-        _check(LIB.ip_plan_create(C.byref(h), C.byref(m), C.byref(g) if g else None,
-                                  IP_F64 if precision == "f64" else IP_F32))
+        self.options = dict(options or {})
+        opt = ip_plan_options(int(self.options.get("unit_nodes", 0)),
+                              int(self.options.get("patch_owned", 0)),
+                              int(self.options.get("tile_bytes", 0)),
+                              int(self.options.get("threads", 0)))
+        _check(LIB.ip_plan_create_ex(C.byref(h), C.byref(m), C.byref(g) if g else None,
+                                     IP_F64 if precision == "f64" else IP_F32, C.byref(opt)))
         self.handle = h
         counts = (C.c_int64 * 4)()
         _check(LIB.ip_plan_sizes(h, counts))
@@ -201,8 +213,10 @@ class Plan:
             pass
 
 
-def ip_plan_create(mesh, grid=None, precision="f64") -> Plan:
-    return Plan(mesh, grid, precision)
+def ip_plan_create(mesh, grid=None, precision="f64", options=None) -> Plan:
+    """options: dict with any of unit_nodes, patch_owned, tile_bytes (see
+    ip_plan_options)."""
+    return Plan(mesh, grid, precision, options)
 
 
 def ip_reference_from(plan: Plan, Xref: torch.Tensor, stream=None) -> Reference:

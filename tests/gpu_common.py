@@ -5,6 +5,7 @@ import torch
 
 import oracle as O
 from paper_1612_03399_amd import native as N
+from paper_1612_03399_amd.workload import subset  # noqa: F401  (re-exported for the tests)
 
 DEV = "cuda"
 
@@ -67,37 +68,6 @@ def elem_rel(y, yhat):
 
 
 TOL = {"f64": 1e-12, "f32": 1e-5}
-
-
-def subset(wl, ids):
-    """The bodies ``ids`` of a workload as a workload of their own (node ids
-    rebased); everything per body is sliced, nothing is recomputed."""
-    import dataclasses
-    ids = [int(b) for b in ids]
-    X, Xr, fa, e4, pn = [], [], [], [], []
-    no, eo, fo = [0], [0], [0]
-    for b in ids:
-        n0, n1 = int(wl.node_off[b]), int(wl.node_off[b + 1])
-        e0, e1 = int(wl.edge_off[b]), int(wl.edge_off[b + 1])
-        f0, f1 = int(wl.face_off[b]), int(wl.face_off[b + 1])
-        base = no[-1]
-        X.append(wl.X[n0:n1])
-        Xr.append(wl.Xref[n0:n1])
-        pn.append(wl.pinned[n0:n1])
-        fa.append(wl.faces[f0:f1] - n0 + base)
-        e = wl.edges4[e0:e1]
-        e4.append(np.where(e >= 0, e - n0 + base, -1))
-        no.append(base + n1 - n0)
-        eo.append(eo[-1] + e1 - e0)
-        fo.append(fo[-1] + f1 - f0)
-    cat = lambda a, t: np.ascontiguousarray(np.concatenate(a).astype(t))
-    return dataclasses.replace(
-        wl, X=cat(X, np.float64), Xref=cat(Xr, np.float64), faces=cat(fa, np.int32),
-        edges4=cat(e4, np.int32), pinned=cat(pn, np.uint8),
-        node_off=np.asarray(no, np.int64), edge_off=np.asarray(eo, np.int64),
-        face_off=np.asarray(fo, np.int64), closed=wl.closed[ids].copy(),
-        ks=wl.ks[ids].copy(), kb=wl.kb[ids].copy(), kA=wl.kA[ids].copy(),
-        kV=wl.kV[ids].copy(), mass=wl.mass[ids].copy())
 
 
 def step_error(wl, Xg, Xo, X0, tol):

@@ -90,3 +90,15 @@ def test_null_arguments_rejected():
     assert N.LIB.ip_forces(None, None, None, None, None, None, None, None, None) == N.IP_ERR_ARG
     assert N.LIB.ip_step(None, None, None, None, None, None, 0.0, None, None, None) == N.IP_ERR_ARG
     assert N.LIB.ip_plan_destroy(None) == N.IP_OK
+
+
+@pytest.mark.parametrize("opts", [(-1, 0, 0, 0), (0, 8, 0, 0), (0, 0, 1024, 0), (0, 0, 0, 512)])
+def test_invalid_plan_options_rejected(opts):
+    wl = W.small_suspension(2, 1, 16)
+    m, keep = _mesh_struct(wl)
+    grid = N.ip_grid(16, 16, 16, 1.0 / 16)
+    h = C.c_void_p()
+    o = N.ip_plan_options(*opts)
+    code = N.LIB.ip_plan_create_ex(C.byref(h), C.byref(m), C.byref(grid), N.IP_F64, C.byref(o))
+    assert code == N.IP_ERR_ARG and not h.value
+    assert "options" in N.LIB.ip_last_error().decode()

@@ -121,13 +121,7 @@ def test_interp_spread_parity(case, precision):
     assert rel_inf(host(f).astype(np.float64), want_f) <= TOL[precision]
 
 
-@pytest.mark.parametrize("bound", [False, True], ids=["explicit_ref", "bound_ref"])
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("case", list(CASES))
-def test_step_parity(case, precision, bound):
-    """One step; with a bound reference the fused step reads the packed,
-    conflict-ordered element records instead of the caller's arrays."""
-    say("step", case, precision, "bound" if bound else "explicit")
+def check_step(case, precision, bound, options=None):
     wl, ref = build(case, precision)
     dt_ = N.real_dtype(precision)
     u = wl.velocity()
@@ -136,7 +130,7 @@ def test_step_parity(case, precision, bound):
     oref = oracle_reference_as_seen(ref, precision)
     f_want = np.zeros_like(u)
     want = O.step(wl, wl.X, oref, u, wl.dt, f_want)
-    plan = N.Plan(wl, wl.grid, precision)
+    plan = N.Plan(wl, wl.grid, precision, options)
     X = dev(wl.X)
     f = torch.zeros(u.shape, dtype=dt_, device=DEV)
     V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
@@ -156,9 +150,39 @@ def test_step_parity(case, precision, bound):
         ulp = np.spacing(np.abs(wl.X[s]).max())
         assert np.abs(Xg[s] - Xo[s]).max() <= TOL[precision] * dx + 2 * ulp
     assert rel_inf(host(f).astype(np.float64), f_want) <= TOL[precision]
+    Vg = host(V)
+    assert elem_rel(Vg[wl.closed == 1], want["V"][wl.closed == 1]) <= 1e-12
     pin = wl.pinned == 1
     if pin.any():
         assert np.array_equal(host(X)[pin], wl.X[pin])
+    return plan
+
+
+@pytest.mark.parametrize("bound", [False, True], ids=["explicit_ref", "bound_ref"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_parity(case, precision, bound):
+    """One step; with a bound reference the fused step reads the packed,
+    conflict-ordered element records instead of the caller's arrays."""
+    say("step", case, precision, "bound" if bound else "explicit")
+    check_step(case, precision, bound)
+
+
+#: launch shapes the autotuner chooses between (all compute the same step)
+LAUNCH_SHAPES = {
+    "t384": {"threads": 384},
+    "t384_small_units": {"threads": 384, "unit_nodes": 640, "patch_owned": 384,
+                         "tile_bytes": 12288},
+    "t768_tile8k": {"tile_bytes": 8192},
+}
+
+
+@pytest.mark.parametrize("shape", list(LAUNCH_SHAPES))
+@pytest.mark.parametrize("case", ["four_L4_128", "uneven_small", "ventricle_patched"])
+def test_step_parity_launch_shapes(case, shape):
+    say("step shape", case, shape)
+    plan = check_step(case, "f64", True, LAUNCH_SHAPES[shape])
+    assert plan.fused and plan.step_threads == LAUNCH_SHAPES[shape].get("threads", 768)
 
 
 def test_forces_deterministic():
