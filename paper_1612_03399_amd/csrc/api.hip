@@ -168,25 +168,56 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
                                        p->device));
     if (lds_optin <= 0) IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin,
                                      hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
-    p->step_threads = opt.threads > 0 ? opt.threads : kStepThreads;
-    const int unit_max = p->step_threads * kStepNodesPerThread;
+    // threads: 0 = large units on 768-thread workgroups and units of at most
+    // 384 x 4 nodes on 384-thread ones (two per compute unit); 768 or 384 =
+    // every unit on that size
+    const int big = opt.threads == 384 ? 384 : 768;
+    const int unit_max = big * kStepNodesPerThread;
     const int unit_nodes = opt.unit_nodes > 0 ? std::min(opt.unit_nodes, unit_max) : unit_max;
-    const int unit_faces = p->step_threads * kStepFacesPerThread;
+    const int unit_faces = big * kStepFacesPerThread;
     const int patch_owned = opt.patch_owned > 0 ? opt.patch_owned : kPatchOwned;
     WorkUnits wu;
     if (B > 0 && build_work_units(m, unit_nodes, unit_max, unit_faces, patch_owned, wu)) {
-        int nmax = 1;
-        for (const auto &u : wu.units) nmax = std::max(nmax, u.n_nodes);
-        // LDS left for the grid tile once positions, accumulators and the
-        // cell list are placed (1 KB kept for the kernel's static LDS)
-        long long tile_bytes =
-            ((long long)lds_optin - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
-        if (opt.tile_bytes > 0) tile_bytes = std::min<long long>(tile_bytes, opt.tile_bytes / 16 * 16);
-        if (tile_bytes >= 4096) {
+        const int W = (int)wu.units.size();
+        // units are sorted by size: the longest suffix of units that fit a
+        // 384-thread workgroup forms the second class
+        int split = W;
+        if (opt.threads == 0)
+            while (split > 0 && wu.units[split - 1].n_nodes <= 384 * kStepNodesPerThread &&
+                   wu.units[split - 1].face_end - wu.units[split - 1].face_begin <=
+                       384 * kStepFacesPerThread)
+                --split;
+        const auto tile_for = [&](int nmax, int share) {
+            // LDS left for the grid tile once positions, accumulators and the
+            // cell list are placed (1 KB kept for the kernel's static LDS),
+            // for `share` workgroups per compute unit
+            long long t = ((long long)lds_optin / share - 1024 - (long long)step_fused_lds_bytes(nmax, 0)) / 16 * 16;
+            if (opt.tile_bytes > 0) t = std::min<long long>(t, opt.tile_bytes / 16 * 16);
+            return std::min<long long>(t, 1 << 20);
+        };
+        bool ok = true;
+        p->n_step_classes = 0;
+        const int bounds[3] = {0, split, W};
+        for (int c = 0; c < 2; ++c) {
+            if (bounds[c + 1] <= bounds[c]) continue;
+            ip_plan::StepClass sc;
+            sc.unit_begin = bounds[c];
+            sc.unit_end = bounds[c + 1];
+            sc.threads = c == 0 ? big : 384;
+            sc.nmax = 1;
+            for (int w = sc.unit_begin; w < sc.unit_end; ++w)
+                sc.nmax = std::max(sc.nmax, wu.units[w].n_nodes);
+            long long t = c == 1 ? tile_for(sc.nmax, 2) : -1;
+            if (t < 4096) t = tile_for(sc.nmax, 1);
+            ok = ok && t >= 4096;
+            sc.tile_bytes = (int)std::max<long long>(t, 0);
+            p->step_class[p->n_step_classes++] = sc;
+        }
+        if (ok) {
             p->fused_all = true;
-            p->fused_nmax = nmax;
-            p->fused_tile_bytes = (int)std::min<long long>(tile_bytes, 1 << 20);
-            const int W = (int)wu.units.size();
+            p->fused_nmax = p->step_class[0].nmax;
+            p->fused_tile_bytes = p->step_class[0].tile_bytes;
+            p->step_threads = p->step_class[0].threads;
             p->n_units = W;
             // ranges as (begin, end) pairs: units are stored largest first,
             // their lists in build order

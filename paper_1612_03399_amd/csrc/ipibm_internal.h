@@ -68,8 +68,16 @@ struct ip_plan {
     // larger one: owned nodes plus the halo its elements reach)
     bool fused_all = false;
     int fused_nmax = 0;           // largest work unit (nodes, owned + halo)
-    int fused_tile_bytes = 0;     // LDS bytes for the per-unit grid tile
-    int step_threads = 768;       // threads per workgroup of the fused step (768 or 384)
+    int fused_tile_bytes = 0;     // LDS bytes for the grid tile (first launch class)
+    int step_threads = 768;       // threads per workgroup (first launch class)
+    // launch classes of the fused step: consecutive ranges of the units
+    // (largest first), each with its own workgroup size and LDS layout
+    struct StepClass {
+        int32_t unit_begin = 0, unit_end = 0;
+        int threads = 768, nmax = 0, tile_bytes = 0;
+    };
+    StepClass step_class[2];
+    int n_step_classes = 0;
     int32_t n_units = 0;
     int32_t *wu_body = nullptr;   // [n_units] body of each unit, largest unit first
     int32_t *wu_owned = nullptr;  // [n_units] owned nodes

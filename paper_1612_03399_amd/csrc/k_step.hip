@@ -53,6 +53,7 @@ struct StepArgs {
     const int32_t *wu_body, *wu_owned, *wu_nodes;
     const int64_t *wu_noff, *wu_eoff, *wu_foff;
     const void *erec, *frec; // packed element records
+    int unit_base;           // unit of workgroup 0 of this launch
     int nmax;                // node capacity of the LDS layout
     int tile_bytes;          // bytes of the tile region
 };
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     __shared__ int cnt_bins[kCountBins + 1];
 
     const int tid = threadIdx.x;
-    const int w = blockIdx.x;
+    const int w = a.unit_base + (int)blockIdx.x;
     const int b = a.wu_body[w];
     const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
     const bool whole = nl1 == nl0;                    // a whole body, nodes contiguous
@@ -782,10 +783,13 @@ const void *step_kernel(int threads) {
 }
 
 ip_status prepare_step_fused(ip_plan *p) {
-    const int lds = (int)step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    const void *fn = p->prec == IP_F64 ? step_kernel<double>(p->step_threads)
-                                       : step_kernel<float>(p->step_threads);
-    IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    for (int c = 0; c < p->n_step_classes; ++c) {
+        const auto &sc = p->step_class[c];
+        const int lds = (int)step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
+        const void *fn = p->prec == IP_F64 ? step_kernel<double>(sc.threads)
+                                           : step_kernel<float>(sc.threads);
+        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    }
     return IP_OK;
 }
 
@@ -827,25 +831,29 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
     a.wu_foff = p->wu_foff;
     a.erec = p->edge_rec;
     a.frec = p->face_rec;
-    a.nmax = p->fused_nmax;
-    a.tile_bytes = p->fused_tile_bytes;
     // volume and area of patched bodies, before their patches need them
     if (p->n_patched_bodies > 0)
         IP_TRY(launch_geometry(p, X, a.V, a.A, s, p->patched_bodies, p->n_patched_bodies));
-    const size_t lds = step_fused_lds_bytes(p->fused_nmax, p->fused_tile_bytes);
-    const int nt = p->step_threads;
-    if (p->prec == IP_F64) {
-        if (nt == 384)
-            hipLaunchKernelGGL((k_step_fused<double, 384>), dim3(p->n_units), dim3(nt), lds, s, a);
-        else
-            hipLaunchKernelGGL((k_step_fused<double, 768>), dim3(p->n_units), dim3(nt), lds, s, a);
-    } else {
-        if (nt == 384)
-            hipLaunchKernelGGL((k_step_fused<float, 384>), dim3(p->n_units), dim3(nt), lds, s, a);
-        else
-            hipLaunchKernelGGL((k_step_fused<float, 768>), dim3(p->n_units), dim3(nt), lds, s, a);
+    for (int c = 0; c < p->n_step_classes; ++c) {
+        const auto &sc = p->step_class[c];
+        a.unit_base = sc.unit_begin;
+        a.nmax = sc.nmax;
+        a.tile_bytes = sc.tile_bytes;
+        const size_t lds = step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
+        const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
+        if (p->prec == IP_F64) {
+            if (sc.threads == 384)
+                hipLaunchKernelGGL((k_step_fused<double, 384>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((k_step_fused<double, 768>), grid, block, lds, s, a);
+        } else {
+            if (sc.threads == 384)
+                hipLaunchKernelGGL((k_step_fused<float, 384>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((k_step_fused<float, 768>), grid, block, lds, s, a);
+        }
+        IP_HIP_CHECK(hipGetLastError());
     }
-    IP_HIP_CHECK(hipGetLastError());
     if (p->n_patched_units > 0) {
         hipLaunchKernelGGL(k_commit, dim3(p->n_patched_units), dim3(256), 0, s, p->patched_units,
                            p->wu_noff, p->wu_owned, p->wu_nodes, p->Xstage, X);
