@@ -261,6 +261,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
             IP_TRY(upload(&p->patched_units, pu.data(), pu.size()));
             if (!pb.empty()) IP_TRY(alloc_bytes((void **)&p->Xstage, (size_t)N * 3 * sizeof(double)));
             IP_TRY(prepare_step_fused(p));
+            if (p->prec == IP_F64) IP_TRY(prepare_step_vjp_fused(p));
         }
     }
     IP_HIP_CHECK(hipDeviceSynchronize());
@@ -488,10 +489,21 @@ ip_status ip_step_vjp(ip_plan *plan, const double *X, const ip_reference *ref,
     if (!aligned(X, 8) || !aligned(u, 8) || !aligned(lam_next, 8) || !aligned(lam, 8) ||
         !aligned(gk, 8) || !aligned(gu, 8))
         return arg_error("misaligned array");
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->fused_all) {
+        // the fused reverse step reads the same packed records as the step
+        const bool bound = ref == &plan->bref;
+        if (!bound || plan->packed != 1) {
+            IP_TRY(launch_pack_reference(plan, ref, s));
+            plan->packed = bound ? 1 : 2;
+        }
+        return launch_step_vjp_fused(plan, X, ref, k, (const double *)u, dt, lam_next, lam, gk,
+                                     (double *)gu, s);
+    }
     if (!plan->bwd_dots && plan->E + plan->F > 0)
         IP_TRY(alloc_bytes((void **)&plan->bwd_dots, (size_t)(plan->E + plan->F) * 2 * sizeof(double)));
     return launch_step_vjp(plan, X, ref, k, (const double *)u, dt, lam_next, lam, gk,
-                           (double *)gu, (hipStream_t)stream);
+                           (double *)gu, s);
 }
 
 ip_status ip_taylor(ip_plan *plan, const double *X, const double *Dstar, double *D,

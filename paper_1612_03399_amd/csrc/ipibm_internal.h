@@ -186,6 +186,14 @@ constexpr int kPatchOwned = 512;         // owned nodes per patch of a large bod
 size_t step_fused_lds_bytes(int nmax, int tile_bytes);
 ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
 ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s);
+// owned nodes of patched units: src -> dst ([N][3] double each)
+ip_status launch_commit(ip_plan *p, const double *src, double *dst, hipStream_t s);
+// fused reverse step (k_backward.hip), FP64 fused plans; records hold `ref`
+ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference *ref,
+                                const ip_constants *k, const double *u, double dt,
+                                const double *lam_in, double *lam_out, double *gk, double *gu,
+                                hipStream_t s);
+ip_status prepare_step_vjp_fused(ip_plan *p);
 ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
                             const ip_constants *k, const void *u, void *f, double dt,
                             double *V, double *A, hipStream_t s);

@@ -12,8 +12,7 @@
 //   dL/dk_s (body b) += (dt^2/m_b) sum_{l in b} (F_s,l / k_s) . P_l
 //   dL/du += dt h^3 spread(P)        (interpolation's adjoint is spreading)
 // F_s is linear in k_s, so F_s/k_s is the family's force at unit constant.
-#include "elements.h"
-#include "ipibm_internal.h"
+#include "step_common.h"
 
 namespace {
 
@@ -270,45 +269,52 @@ __global__ void k_scale(const double *__restrict__ P, double s, int64_t n, doubl
 
 // ---------------------------------------------------------------------------
 // Taylor deformation: C = (1/n) sum (x - c)(x - c)^T over the body's nodes;
-// eigenvalues of the symmetric 3x3 C in closed form (trigonometric solution
-// of the characteristic cubic), L = sqrt(lambda_max), B = sqrt(lambda_min),
-// D = (L - B)/(L + B).  Eigenvectors from cross products of rows of C - lambda I.
+// eigenvalues and eigenvectors of the symmetric 3x3 C by Jacobi rotations,
+// L = sqrt(lambda_max), B = sqrt(lambda_min), D = (L - B)/(L + B).
 // ---------------------------------------------------------------------------
 struct Sym3 {
     double xx, yy, zz, xy, xz, yz;
 };
 
-__device__ void sym3_eigs(const Sym3 &A, double lam[3]) {
-    const double p1 = A.xy * A.xy + A.xz * A.xz + A.yz * A.yz;
-    const double q = (A.xx + A.yy + A.zz) / 3.0;
-    const double dx = A.xx - q, dy = A.yy - q, dz = A.zz - q;
-    const double p2 = dx * dx + dy * dy + dz * dz + 2.0 * p1;
-    const double p = sqrt(p2 / 6.0);
-    if (p == 0.0) {
-        lam[0] = lam[1] = lam[2] = q;
-        return;
+// Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations
+// (each rotation annihilates one off-diagonal entry; sweeps until every
+// off-diagonal entry is negligible against its diagonal pair, which keeps the
+// small eigenvalues of a nearly flat body accurate relative to themselves).
+// lam[k] with eigenvector column vec[.][k].
+__device__ void sym3_jacobi(const Sym3 &C, double lam[3], double vec[3][3]) {
+    double m[3][3] = {{C.xx, C.xy, C.xz}, {C.xy, C.yy, C.yz}, {C.xz, C.yz, C.zz}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) vec[i][j] = i == j ? 1.0 : 0.0;
+    const int P[3] = {0, 0, 1}, Q[3] = {1, 2, 2};
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        bool rotated = false;
+        for (int k = 0; k < 3; ++k) {
+            const int p = P[k], q = Q[k];
+            const double apq = m[p][q];
+            if (apq == 0.0 || fabs(apq) <= 1e-18 * sqrt(fabs(m[p][p] * m[q][q]))) {
+                m[p][q] = m[q][p] = 0.0;
+                continue;
+            }
+            rotated = true;
+            const double theta = (m[q][q] - m[p][p]) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+            m[p][p] -= t * apq;
+            m[q][q] += t * apq;
+            m[p][q] = m[q][p] = 0.0;
+            const int r = 3 - p - q;
+            const double arp = m[r][p], arq = m[r][q];
+            m[r][p] = m[p][r] = c * arp - sn * arq;
+            m[r][q] = m[q][r] = sn * arp + c * arq;
+            for (int i = 0; i < 3; ++i) {
+                const double vp = vec[i][p], vq = vec[i][q];
+                vec[i][p] = c * vp - sn * vq;
+                vec[i][q] = sn * vp + c * vq;
+            }
+        }
+        if (!rotated) break;
     }
-    const double ip = 1.0 / p;
-    const double bxx = dx * ip, byy = dy * ip, bzz = dz * ip, bxy = A.xy * ip, bxz = A.xz * ip,
-                 byz = A.yz * ip;
-    const double detB = bxx * (byy * bzz - byz * byz) - bxy * (bxy * bzz - byz * bxz) +
-                        bxz * (bxy * byz - byy * bxz);
-    double r = detB / 2.0;
-    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
-    const double phi = acos(r) / 3.0;
-    lam[0] = q + 2.0 * p * cos(phi);                              // largest
-    lam[2] = q + 2.0 * p * cos(phi + 2.0 * 3.14159265358979323846 / 3.0);   // smallest
-    lam[1] = 3.0 * q - lam[0] - lam[2];
-}
-
-__device__ vec3<double> sym3_eigvec(const Sym3 &A, double l) {
-    const vec3<double> r0 = {A.xx - l, A.xy, A.xz}, r1 = {A.xy, A.yy - l, A.yz},
-                       r2 = {A.xz, A.yz, A.zz - l};
-    vec3<double> c0 = cross(r0, r1), c1 = cross(r0, r2), c2 = cross(r1, r2);
-    const double n0 = dot(c0, c0), n1 = dot(c1, c1), n2 = dot(c2, c2);
-    vec3<double> v = n0 >= n1 && n0 >= n2 ? c0 : (n1 >= n2 ? c1 : c2);
-    const double n = sqrt(dot(v, v));
-    return (1.0 / n) * v;
+    for (int k = 0; k < 3; ++k) lam[k] = m[k][k];
 }
 
 // Per body: D[b]; with Dstar, also loss[b] = (D - D*)^2 and gX = dloss/dX.
@@ -352,9 +358,14 @@ __global__ __launch_bounds__(256) void k_taylor(const double *__restrict__ X,
     for (int c = 0; c < 6; ++c) acc[c] = block_sum(acc[c], sh);
     if (threadIdx.x == 0) {
         const Sym3 C = {acc[0] / n, acc[1] / n, acc[2] / n, acc[3] / n, acc[4] / n, acc[5] / n};
-        double lam[3];
-        sym3_eigs(C, lam);
-        const double L = sqrt(lam[0]), Bs = sqrt(lam[2]);
+        double lam[3], vec[3][3];
+        sym3_jacobi(C, lam, vec);
+        int kx = 0, kn = 0;
+        for (int q = 1; q < 3; ++q) {
+            if (lam[q] > lam[kx]) kx = q;
+            if (lam[q] < lam[kn]) kn = q;
+        }
+        const double L = sqrt(lam[kx]), Bs = sqrt(fmax(lam[kn], 0.0));
         const double Db = (L - Bs) / (L + Bs);
         if (D) D[b] = Db;
         if (Dstar) {
@@ -362,7 +373,8 @@ __global__ __launch_bounds__(256) void k_taylor(const double *__restrict__ X,
             loss[b] = r * r;
             const double dDdL = 2.0 * Bs / ((L + Bs) * (L + Bs));
             const double dDdB = -2.0 * L / ((L + Bs) * (L + Bs));
-            const vec3<double> vmax = sym3_eigvec(C, lam[0]), vmin = sym3_eigvec(C, lam[2]);
+            const vec3<double> vmax = {vec[0][kx], vec[1][kx], vec[2][kx]};
+            const vec3<double> vmin = {vec[0][kn], vec[1][kn], vec[2][kn]};
             bc[3] = 2.0 * r * dDdL / (2.0 * L);       // dloss/dlambda_max
             bc[4] = 2.0 * r * dDdB / (2.0 * Bs);      // dloss/dlambda_min
             bc[5] = vmax.x; bc[6] = vmax.y; bc[7] = vmax.z;
@@ -379,6 +391,369 @@ __global__ __launch_bounds__(256) void k_taylor(const double *__restrict__ X,
         gX[3 * m] = a * vmax.x + c * vmin.x;
         gX[3 * m + 1] = a * vmax.y + c * vmin.y;
         gX[3 * m + 2] = a * vmax.z + c * vmin.z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused reverse step: one workgroup per work unit, the same units, packed
+// records and LDS layout as the fused forward step.  With P = M lam' (the
+// adjoint of the new positions, pinned rows zeroed) read from memory:
+//  P0  positions -> LDS, accumulators dF zeroed, cell box of the owned nodes.
+//  P1  volume V and its tangent dV along P (a whole body; patched bodies'
+//      come from a pass before this kernel).
+//  P2  every element in dual numbers at unit constants, tangent P: the
+//      tangents scaled by k_s go into dF = (dF/dX) P, the values dotted with
+//      P give the constants' gradients (each element counted by the unit that
+//      owns its first node).
+//  P2b lam = lam' + dt^2/m dF for the owned nodes, held in registers.
+//  P3  P' = dt h^3 P of the owned nodes replaces dF in LDS; counting sort by
+//      cell as in the forward step.
+//  P4  gu += spread(P') = dt sum P w (the adjoint of interpolation).
+//  P5  per lattice: the velocity tile is staged, every owned node adds
+//      sum_d P'_d dU_d/dX = dt h^3 (J_U^T P); lam += that / h^3 is written.
+// ---------------------------------------------------------------------------
+struct VjpArgs {
+    const double *X, *lam_in;
+    double *lam_out;           // whole units; patched units write lam_stage
+    double *lam_stage;
+    const int64_t *node_off;
+    const uint8_t *closed, *pinned;
+    const double *V0, *ks, *kb, *kA, *kV, *mass;
+    const double *u;
+    double *gu, *gk;
+    int B;
+    int nx, ny, nz;
+    double inv_h, inv_h3;
+    int64_t plane, field;
+    double dt;
+    const double *Vpre, *dVpre;   // patched bodies: volume and its tangent
+    uint32_t *status;
+    const int32_t *wu_body, *wu_owned, *wu_nodes;
+    const int64_t *wu_noff, *wu_eoff, *wu_foff;
+    const void *erec, *frec;
+    int unit_base, nmax, tile_bytes;
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ double red[NT / 64];
+    __shared__ int ired[NT / 64];
+    __shared__ double bcd[2];
+    __shared__ int n_occ_sh;
+    __shared__ int cnt_bins[kCountBins + 1];
+
+    const int tid = threadIdx.x;
+    const int w = a.unit_base + (int)blockIdx.x;
+    const int b = a.wu_body[w];
+    const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
+    const bool whole = nl1 == nl0;
+    const int64_t n0 = a.node_off[b];
+    const int NL = whole ? (int)(a.node_off[b + 1] - n0) : (int)(nl1 - nl0);
+    const int N = whole ? NL : a.wu_owned[w];
+    const int32_t *gid = a.wu_nodes + nl0;
+    const int64_t e0 = a.wu_eoff[2 * w];
+    const int E = (int)(a.wu_eoff[2 * w + 1] - e0);
+    const int64_t f0 = a.wu_foff[2 * w];
+    const int F = (int)(a.wu_foff[2 * w + 1] - f0);
+    if (NL == 0) return;
+
+    double *xs = (double *)lds;
+    double *dF = xs + 3 * a.nmax;                     // dF, then P' (P3 onwards)
+    unsigned char *tile_region = (unsigned char *)(dF + 3 * a.nmax);
+    double *ftile = (double *)tile_region;
+    double *utile = (double *)tile_region;
+    uint16_t *occ_start = (uint16_t *)(tile_region + a.tile_bytes);
+    uint16_t *occ_cnt = occ_start + a.nmax;
+    bool bad = false;
+    const double c2 = a.dt * a.dt / a.mass[b];
+    const auto gnode = [&](int l) -> int64_t { return whole ? n0 + l : (int64_t)gid[l]; };
+    const auto tangent = [&](int l) -> vec3<double> {   // P of unit node l
+        const int64_t g = gnode(l);
+        if (a.pinned[g]) return {0.0, 0.0, 0.0};
+        return {a.lam_in[3 * g], a.lam_in[3 * g + 1], a.lam_in[3 * g + 2]};
+    };
+    const auto dualx = [&](int l, const vec3<double> &t) -> vec3<dual> {
+        return {dual(xs[3 * l], t.x), dual(xs[3 * l + 1], t.y), dual(xs[3 * l + 2], t.z)};
+    };
+    const auto addd = [&](int l, double k, const vec3<dual> &v) {
+        lds_add(dF + 3 * l, k * v.x.d);
+        lds_add(dF + 3 * l + 1, k * v.y.d);
+        lds_add(dF + 3 * l + 2, k * v.z.d);
+    };
+
+    int fi[FK][3];
+    double fa0[FK];
+    unsigned fmask = 0;
+#pragma unroll
+    for (int s = 0; s < FK; ++s) {
+        const int t = tid + s * NT;
+        fi[s][0] = fi[s][1] = fi[s][2] = 0;
+        fa0[s] = 1.0;
+        if (t < F) {
+            fmask |= 1u << s;
+            const int4 r = ((const int4 *)a.frec)[f0 + t];
+            fi[s][0] = r.x & 0xFFFF;
+            fi[s][1] = (int)((unsigned)r.x >> 16);
+            fi[s][2] = r.y & 0xFFFF;
+            fa0[s] = face_a0(r, 0.0);
+        }
+    }
+
+    // ---- P0 ----
+    for (int i = tid; i < 3 * NL; i += NT) dF[i] = 0.0;
+    int kmin[3], kmax[3];
+    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, ired, kmin, kmax);
+
+    // ---- P1: V and dV ----
+    double Vb, dVb;
+    if (whole) {
+        const vec3<dual> anchor = dualx(0, tangent(0));
+        double v6 = 0.0, dv6 = 0.0;
+#pragma unroll
+        for (int s = 0; s < FK; ++s) {
+            if (fmask & (1u << s)) {
+                dual v;
+                double ar;
+                face_geometry<dual, double>(dualx(fi[s][0], tangent(fi[s][0])),
+                                            dualx(fi[s][1], tangent(fi[s][1])),
+                                            dualx(fi[s][2], tangent(fi[s][2])), anchor, v, ar);
+                v6 += v.v;
+                dv6 += v.d;
+            }
+        }
+        v6 = block_sum(v6, red);
+        dv6 = block_sum(dv6, red);
+        if (tid == 0) {
+            bcd[0] = v6 * (1.0 / 6.0);
+            bcd[1] = dv6 * (1.0 / 6.0);
+        }
+        __syncthreads();
+        Vb = bcd[0];
+        dVb = bcd[1];
+    } else {
+        Vb = a.Vpre[b];
+        dVb = a.dVpre[b];
+    }
+
+    // ---- P2: elements (dual numbers, unit constants) ----
+    double dot_s = 0.0, dot_b = 0.0, dot_a = 0.0, dot_v = 0.0;
+    {
+        const double kA = a.kA[b], kV = a.kV[b], ks = a.ks[b], kb = a.kb[b];
+        const dual sV1 = volume_coefficient<dual>(a.closed[b] != 0, 1.0, dual(Vb, dVb), a.V0[b]);
+#pragma unroll
+        for (int s = 0; s < FK; ++s) {
+            if (fmask & (1u << s)) {
+                const int i = fi[s][0], j = fi[s][1], k = fi[s][2];
+                const vec3<double> pi = tangent(i), pj = tangent(j), pk = tangent(k);
+                vec3<dual> gi, gj, gk, gv;
+                bad |= face_parts<dual, dual>(dualx(i, pi), dualx(j, pj), dualx(k, pk),
+                                              dual(fa0[s]), 1.0, sV1, gi, gj, gk, gv);
+                addd(i, kA, gi);
+                addd(j, kA, gj);
+                addd(k, kA, gk);
+                addd(i, kV, gv);
+                addd(j, kV, gv);
+                addd(k, kV, gv);
+                if (whole || i < N) {
+                    dot_a += gi.x.v * pi.x + gi.y.v * pi.y + gi.z.v * pi.z + gj.x.v * pj.x +
+                             gj.y.v * pj.y + gj.z.v * pj.z + gk.x.v * pk.x + gk.y.v * pk.y +
+                             gk.z.v * pk.z;
+                    dot_v += gv.x.v * (pi.x + pj.x + pk.x) + gv.y.v * (pi.y + pj.y + pk.y) +
+                             gv.z.v * (pi.z + pj.z + pk.z);
+                }
+            }
+        }
+        using Raw = RawEdge<double>;
+        for (int t = tid; t < E; t += NT) {
+            const Raw r = Raw::load(a.erec, (int)e0 + t);
+            const int4 q = r.ids();
+            const bool hinge = q.z != kNoNode && q.w != kNoNode;
+            const vec3<double> p1 = tangent(q.x), p2 = tangent(q.y);
+            const vec3<double> p3 = hinge ? tangent(q.z) : vec3<double>{0.0, 0.0, 0.0};
+            const vec3<double> p4 = hinge ? tangent(q.w) : vec3<double>{0.0, 0.0, 0.0};
+            const vec3<dual> x1 = dualx(q.x, p1), x2 = dualx(q.y, p2);
+            const vec3<dual> x3 = dualx(hinge ? q.z : 0, p3), x4 = dualx(hinge ? q.w : 0, p4);
+            vec3<dual> fsp, h1, h2, h3, h4;
+            bad |= edge_parts<dual, dual>(x1, x2, x3, x4, hinge, dual(r.l0()), dual(r.c0()),
+                                          dual(r.s0()), 1.0, 1.0, fsp, h1, h2, h3, h4);
+            addd(q.x, ks, fsp);
+            addd(q.y, -ks, fsp);
+            if (hinge) {
+                addd(q.x, kb, h1);
+                addd(q.y, kb, h2);
+                addd(q.z, kb, h3);
+                addd(q.w, kb, h4);
+            }
+            if (whole || q.x < N) {
+                dot_s += fsp.x.v * (p1.x - p2.x) + fsp.y.v * (p1.y - p2.y) + fsp.z.v * (p1.z - p2.z);
+                if (hinge)
+                    dot_b += h1.x.v * p1.x + h1.y.v * p1.y + h1.z.v * p1.z + h2.x.v * p2.x +
+                             h2.y.v * p2.y + h2.z.v * p2.z + h3.x.v * p3.x + h3.y.v * p3.y +
+                             h3.z.v * p3.z + h4.x.v * p4.x + h4.y.v * p4.y + h4.z.v * p4.z;
+            }
+        }
+    }
+    dot_s = block_sum(dot_s, red);
+    dot_b = block_sum(dot_b, red);
+    dot_a = block_sum(dot_a, red);
+    dot_v = block_sum(dot_v, red);
+    if (tid == 0 && a.gk) {
+        atomicAdd(a.gk + b, c2 * dot_s);
+        atomicAdd(a.gk + a.B + b, c2 * dot_b);
+        atomicAdd(a.gk + 2 * a.B + b, c2 * dot_a);
+        atomicAdd(a.gk + 3 * a.B + b, c2 * dot_v);
+    }
+    __syncthreads();      // dF complete
+
+    // ---- P2b + P3: lam = lam' + dt^2/m dF written for the owned nodes, and
+    // their dF replaced in place by P' = dt h^3 P (each thread its own nodes).
+    // A whole unit may update lam' in place: no other unit reads its nodes,
+    // and this unit reads no tangent after this point. ----
+    double *dst = whole ? a.lam_out : a.lam_stage;
+    const double sc = a.dt / a.inv_h3;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int j = tid + s * NT;
+        if (j < N) {
+            const int64_t g = gnode(j);
+            const bool pin = a.pinned[g] != 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double l = a.lam_in[3 * g + c];
+                dst[3 * g + c] = l + c2 * dF[3 * j + c];
+                dF[3 * j + c] = pin ? 0.0 : sc * l;
+            }
+        }
+    }
+    __syncthreads();
+    int pos[K];
+    const CellSort cs = cell_sort<NT>(xs, dF, N, kmin, kmax, a.inv_h, tile_region, a.tile_bytes,
+                                      occ_start, occ_cnt, ired, &n_occ_sh, cnt_bins, pos, a.nx,
+                                      a.ny, a.nz, a.plane);
+    const TileGeom &tg = cs.tg;
+
+    // ---- P4: gu += spread(P') ----
+    if (a.gu != nullptr)
+        spread_to_grid<double, NT>(xs, dF, N, cs, occ_start, occ_cnt, ftile, a.gu, a.field,
+                                   a.inv_h, a.inv_h3, bad);
+
+    // ---- P5: J_U^T P' per owned node, one lattice at a time ----
+    double gacc[K][3];
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gacc[s][c] = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double *ud = a.u + d * a.field;
+        if (cs.use_tile) {
+            stage_tile<NT>(utile, ud, tg);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const int j = tid + s * NT;
+            if (j >= N) continue;
+            const int p = pos[s];
+            double w[3][3], dw[3][3];
+            int cc[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                cc[ax] = delta3_d(xs[3 * p + ax] * a.inv_h - mac_off(d, ax), w[ax], dw[ax]);
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+            if (cs.use_tile) {
+                const int lx = cc[0] - tg.kmin[0], ly = cc[1] - tg.kmin[1], lz = cc[2] - tg.kmin[2];
+                if (lx < 0 || ly < 0 || lz < 0 || lx + 2 >= tg.Tx || ly + 2 >= tg.Ty ||
+                    lz + 2 >= tg.Tz) {
+                    bad = true;
+                } else {
+#pragma unroll
+                    for (int z = 0; z < 3; ++z)
+#pragma unroll
+                        for (int y = 0; y < 3; ++y) {
+                            const double *row = utile + ((lz + z) * tg.Ty + (ly + y)) * tg.Tx + lx;
+#pragma unroll
+                            for (int x = 0; x < 3; ++x) {
+                                const double uv = row[x];
+                                gx += uv * dw[0][x] * w[1][y] * w[2][z];
+                                gy += uv * w[0][x] * dw[1][y] * w[2][z];
+                                gz += uv * w[0][x] * w[1][y] * dw[2][z];
+                            }
+                        }
+                }
+            } else {
+#pragma unroll
+                for (int z = 0; z < 3; ++z)
+#pragma unroll
+                    for (int y = 0; y < 3; ++y) {
+                        const double *row = ud + wrapi(cc[2] - 1 + z, a.nz) * a.plane +
+                                            (int64_t)wrapi(cc[1] - 1 + y, a.ny) * a.nx;
+#pragma unroll
+                        for (int x = 0; x < 3; ++x) {
+                            const double uv = row[wrapi(cc[0] - 1 + x, a.nx)];
+                            gx += uv * dw[0][x] * w[1][y] * w[2][z];
+                            gy += uv * w[0][x] * dw[1][y] * w[2][z];
+                            gz += uv * w[0][x] * w[1][y] * dw[2][z];
+                        }
+                    }
+            }
+            const double pd = dF[3 * p + d] * a.inv_h;    // P'_d d/dX = P'_d (1/h) d/ds
+            gacc[s][0] += pd * gx;
+            gacc[s][1] += pd * gy;
+            gacc[s][2] += pd * gz;
+        }
+        if (cs.use_tile) __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int j = tid + s * NT;
+        if (j < N) {
+            const int64_t g = gnode(j);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double v = dst[3 * g + c] + gacc[s][c] * a.inv_h3;
+                if (!isfinite(v)) atomicOr(a.status, IP_STATUS_NONFINITE);
+                dst[3 * g + c] = v;
+            }
+        }
+    }
+    if (bad) atomicOr(a.status, IP_STATUS_DEGENERATE);
+}
+
+// Volume and its tangent along P = M lam' of the listed bodies.
+__global__ __launch_bounds__(256) void k_volume_dual_masked(
+    const double *__restrict__ X, const double *__restrict__ lam, const uint8_t *__restrict__ pinned,
+    const int32_t *__restrict__ faces, const int64_t *__restrict__ node_off,
+    const int64_t *__restrict__ face_off, const int32_t *__restrict__ bodies,
+    double *__restrict__ V, double *__restrict__ dV) {
+    __shared__ double sh[4];
+    const int b = bodies[blockIdx.x];
+    if (face_off[b] == face_off[b + 1]) {
+        if (threadIdx.x == 0) V[b] = dV[b] = 0.0;
+        return;
+    }
+    const auto xd = [&](int64_t i) -> vec3<dual> {
+        const bool pin = pinned[i] != 0;
+        return {dual(X[3 * i], pin ? 0.0 : lam[3 * i]), dual(X[3 * i + 1], pin ? 0.0 : lam[3 * i + 1]),
+                dual(X[3 * i + 2], pin ? 0.0 : lam[3 * i + 2])};
+    };
+    const vec3<dual> anchor = xd(node_off[b]);
+    double v = 0.0, dv = 0.0;
+    for (int64_t f = face_off[b] + threadIdx.x; f < face_off[b + 1]; f += blockDim.x) {
+        const int32_t *t = faces + 3 * f;
+        dual v6;
+        double a2;
+        face_geometry<dual, double>(xd(t[0]), xd(t[1]), xd(t[2]), anchor, v6, a2);
+        v += v6.v;
+        dv += v6.d;
+    }
+    v = block_sum(v, sh);
+    dv = block_sum(dv, sh);
+    if (threadIdx.x == 0) {
+        V[b] = v / 6.0;
+        dV[b] = dv / 6.0;
     }
 }
 
@@ -445,4 +820,79 @@ ip_status launch_taylor(ip_plan *p, const double *X, const double *Dstar, double
     hipLaunchKernelGGL(k_taylor, dim3(p->B), dim3(256), 0, s, X, p->node_off, Dstar, D, loss, gX);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
+}
+
+ip_status prepare_step_vjp_fused(ip_plan *p) {
+    for (int c = 0; c < p->n_step_classes; ++c) {
+        const auto &sc = p->step_class[c];
+        const int lds = (int)step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
+        const void *fn = sc.threads == 384 ? (const void *)k_step_vjp_fused<384>
+                                           : (const void *)k_step_vjp_fused<768>;
+        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    }
+    return IP_OK;
+}
+
+ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference *ref,
+                                const ip_constants *k, const double *u, double dt,
+                                const double *lam_in, double *lam_out, double *gk, double *gu,
+                                hipStream_t s) {
+    if (p->B == 0) return IP_OK;
+    VjpArgs a{};
+    a.X = X;
+    a.lam_in = lam_in;
+    a.lam_out = lam_out;
+    a.lam_stage = p->Xstage;
+    a.node_off = p->node_off;
+    a.closed = p->closed;
+    a.pinned = p->pinned;
+    a.V0 = ref->V0;
+    a.ks = k->ks;
+    a.kb = k->kb;
+    a.kA = k->kA;
+    a.kV = k->kV;
+    a.mass = k->mass;
+    a.u = u;
+    a.gu = gu;
+    a.gk = gk;
+    a.B = p->B;
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.inv_h = 1.0 / p->grid.h;
+    a.inv_h3 = 1.0 / (p->grid.h * p->grid.h * p->grid.h);
+    a.plane = (int64_t)a.nx * a.ny;
+    a.field = a.plane * a.nz;
+    a.dt = dt;
+    a.Vpre = p->Vbuf;
+    a.dVpre = p->Abuf;
+    a.status = p->status;
+    a.wu_body = p->wu_body;
+    a.wu_owned = p->wu_owned;
+    a.wu_nodes = p->wu_nodes;
+    a.wu_noff = p->wu_noff;
+    a.wu_eoff = p->wu_eoff;
+    a.wu_foff = p->wu_foff;
+    a.erec = p->edge_rec;
+    a.frec = p->face_rec;
+    if (p->n_patched_bodies > 0) {
+        hipLaunchKernelGGL(k_volume_dual_masked, dim3(p->n_patched_bodies), dim3(256), 0, s, X,
+                           lam_in, p->pinned, p->faces, p->node_off, p->face_off,
+                           p->patched_bodies, p->Vbuf, p->Abuf);
+        IP_HIP_CHECK(hipGetLastError());
+    }
+    for (int c = 0; c < p->n_step_classes; ++c) {
+        const auto &sc = p->step_class[c];
+        a.unit_base = sc.unit_begin;
+        a.nmax = sc.nmax;
+        a.tile_bytes = sc.tile_bytes;
+        const size_t lds = step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
+        const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
+        if (sc.threads == 384)
+            hipLaunchKernelGGL(k_step_vjp_fused<384>, grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL(k_step_vjp_fused<768>, grid, block, lds, s, a);
+        IP_HIP_CHECK(hipGetLastError());
+    }
+    return launch_commit(p, p->Xstage, lam_out, s);
 }

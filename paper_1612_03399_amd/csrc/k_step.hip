@@ -1,39 +1,31 @@
-// k_step.hip -- the fused explicit step, one workgroup per body.
+// k_step.hip -- the fused explicit step, one workgroup per work unit (a whole
+// body, or a patch of a larger body: its owned nodes plus the halo its
+// elements reach).
 //
-// LDS (per workgroup): positions xs[N][3] (FP64), force accumulators
-// Fs[N][3] (FP64 for every plan precision: FP32 LDS atomics are an order of
+// LDS (per workgroup): positions xs[n][3] (FP64), force accumulators
+// Fs[n][3] (FP64 for every plan precision: FP32 LDS atomics are an order of
 // magnitude slower than FP64 ones on gfx950), a tile region for the cell
 // histogram and the per-lattice grid tiles, and the occupied-cell list.
 //
-// Phases (every body is independent; no inter-workgroup communication except
-// the additions into the grid force field):
-//  P0  positions -> LDS and owner registers; cell bounding box (the per-marker
+// Phases (units are independent; no inter-workgroup communication except the
+// additions into the grid force field):
+//  P0  positions -> LDS; cell bounding box of the owned nodes (the per-marker
 //      cell index and the body bounding box of Section 5).
-//  P1  enclosed volume and area of the body (FP64 block reduction).
-//  P2  face (area + volume) and edge (spring + hinge) elements, their forces
-//      added into the node accumulators (ds_add_f64).  Element data for the
-//      next iteration is loaded while the current one is computed.
-//  P3  counting sort of the nodes by Eulerian cell; xs and Fs are permuted in
-//      place into cell order so each occupied cell's nodes are contiguous.
-//  P4  spreading, per lattice: each occupied cell sums its nodes' force-
-//      weighted stencils in registers over the cell's 4x3x3 block, adds the
-//      block to an FP64 LDS tile, and the tile's non-zero points are added to
-//      the grid with device atomics.
-//  P5  per lattice d: the velocity tile is staged in LDS, every node
-//      interpolates U_d from its 27-point stencil and writes
+//  P1  enclosed volume and area of a whole body (FP64 block reduction); a
+//      patched body's come from a geometry pass before this kernel.
+//  P2  face (area + volume) and edge (spring + hinge) elements from the packed
+//      records, their forces added into the node accumulators (ds_add_f64).
+//  P3  counting sort of the owned nodes by Eulerian cell; xs and Fs are
+//      permuted in place into cell order.
+//  P4  spreading, per lattice, through an FP64 LDS tile (step_common.h).
+//  P5  per lattice d: the velocity tile is staged in LDS, every owned node
+//      interpolates U_d from its 27-point stencil and gets the new coordinate
 //      X_d + dt U_d + dt^2/m F_d (nodes that are not pinned).
-// Bodies whose tile does not fit the tile region interpolate and spread
+// Units whose tile does not fit the tile region interpolate and spread
 // directly against the grid (same arithmetic, global atomics).
-#include <climits>
-
-#include "elements.h"
-#include "ipibm_internal.h"
+#include "step_common.h"
 
 namespace {
-
-constexpr int K = kStepNodesPerThread;
-constexpr int kCountBins = 32;     // occupied cells are ordered by node count (capped)
-constexpr int FK = kStepFacesPerThread;
 
 struct StepArgs {
     double *X;
@@ -57,235 +49,6 @@ struct StepArgs {
     int nmax;                // node capacity of the LDS layout
     int tile_bytes;          // bytes of the tile region
 };
-
-__device__ __forceinline__ void lds_add(double *p, double v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ vec3<double> ldx(const double *xs, int i) {
-    return {xs[3 * i], xs[3 * i + 1], xs[3 * i + 2]};
-}
-
-template <typename R>
-__device__ __forceinline__ void add3(double *F, int i, const vec3<R> &v) {
-    lds_add(F + 3 * i, (double)v.x);
-    lds_add(F + 3 * i + 1, (double)v.y);
-    lds_add(F + 3 * i + 2, (double)v.z);
-}
-
-// Cell of a coordinate: the stencil centre of the lattices staggered by half a
-// cell along this axis, computed with exactly the expression delta3() uses.
-__device__ __forceinline__ int cell_of(double x, double inv_h) {
-    double c = floor((x * inv_h - 0.5) + 0.5);
-    if (!(fabs(c) < 1.0e9)) c = 0.0;
-    return (int)c;
-}
-
-// Block-wide minimum / maximum of an int (every thread gets the result).
-template <int NT, bool MAX>
-__device__ __forceinline__ int block_extreme_int(int v, int *sh) {
-    const auto pick = [](int x, int y) { return MAX ? max(x, y) : min(x, y); };
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = pick(v, __shfl_xor(v, o, 64));
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    int r = sh[0];
-    for (int w = 1; w < NT / 64; ++w) r = pick(r, sh[w]);
-    return r;
-}
-
-template <int NT>
-__device__ __forceinline__ int block_min_int(int v, int *sh) { return block_extreme_int<NT, false>(v, sh); }
-template <int NT>
-__device__ __forceinline__ int block_max_int(int v, int *sh) { return block_extreme_int<NT, true>(v, sh); }
-
-// In-place exclusive scan of a[0..n) by the whole block; returns the total.
-template <int NT>
-__device__ int block_exclusive_scan(int *a, int n, int *sh) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int chunk = (n + NT - 1) / NT;
-    const int lo = min(tid * chunk, n), hi = min(lo + chunk, n);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += a[i];
-    int incl = s;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
-    __syncthreads();
-    if (lane == 63) sh[wave] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int w = 0; w < NT / 64; ++w) {
-        if (w < wave) before += sh[w];
-        total += sh[w];
-    }
-    int run = before + incl - s;
-    for (int i = lo; i < hi; ++i) {
-        const int v = a[i];
-        a[i] = run;
-        run += v;
-    }
-    __syncthreads();
-    return total;
-}
-
-// Copy n values from global memory to LDS, U loads in flight per thread.
-template <int NT, typename T, int U = 8>
-__device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__restrict__ src, int n) {
-    for (int base = 0; base < n; base += NT * U) {
-        T v[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int i = base + k * NT + (int)threadIdx.x;
-            v[k] = i < n ? src[i] : (T)0;
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int i = base + k * NT + (int)threadIdx.x;
-            if (i < n) dst[i] = v[k];
-        }
-    }
-}
-
-struct TileGeom {
-    int kmin[3];            // lowest occupied cell per axis
-    int Tx, Ty, Tz, T;      // the tile spans points kmin-1 .. kmax+2
-    int nx, ny, nz;
-    int64_t plane;
-    __device__ __forceinline__ int64_t grid_index(int t) const {
-        const int tx = t % Tx, ty = (t / Tx) % Ty, tz = t / (Tx * Ty);
-        return wrapi(kmin[2] - 1 + tz, nz) * plane + (int64_t)wrapi(kmin[1] - 1 + ty, ny) * nx +
-               wrapi(kmin[0] - 1 + tx, nx);
-    }
-};
-
-// Stage the tile of one grid field into LDS, U loads in flight per thread.
-template <int NT, typename R, int U = 8>
-__device__ __forceinline__ void stage_tile(R *__restrict__ tile, const R *__restrict__ field,
-                                           const TileGeom &g) {
-    for (int base = 0; base < g.T; base += NT * U) {
-        R v[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int t = base + k * NT + (int)threadIdx.x;
-            v[k] = t < g.T ? field[g.grid_index(t)] : (R)0;
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int t = base + k * NT + (int)threadIdx.x;
-            if (t < g.T) tile[t] = v[k];
-        }
-    }
-}
-
-template <int D>
-struct BlockDims {
-    static constexpr int LX = D == 0 ? 4 : 3;
-    static constexpr int LY = D == 1 ? 4 : 3;
-    static constexpr int LZ = D == 2 ? 4 : 3;
-};
-
-// Spread the (cell-contiguous) nodes p0..p1 of one cell on lattice D into the
-// LDS tile: their force-weighted stencils are summed in registers over the
-// cell's 4x3x3 block (4 points along the lattice's unstaggered axis, whose
-// stencil centre may be the cell or the next one) and the block is added to
-// the tile once.
-template <typename R, int D>
-__device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, int p0, int p1,
-                                            const int kc[3], const int kmin[3], int Tx, int Ty,
-                                            int T, double inv_h, double inv_h3, double *tile,
-                                            bool &bad) {
-    using Dm = BlockDims<D>;
-    R acc[Dm::LZ][Dm::LY][Dm::LX];
-#pragma unroll
-    for (int z = 0; z < Dm::LZ; ++z)
-#pragma unroll
-        for (int y = 0; y < Dm::LY; ++y)
-#pragma unroll
-            for (int x = 0; x < Dm::LX; ++x) acc[z][y][x] = 0;
-    for (int p = p0; p < p1; ++p) {
-        R wx[4], wy[4], wz[4];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            R w3[3];
-            const int c = delta3<R>(xs[3 * p + ax] * inv_h - mac_off(D, ax), w3);
-            const int sh = c - kc[ax];
-            R *w = ax == 0 ? wx : (ax == 1 ? wy : wz);
-            if (ax == D) {
-                const bool s1 = sh == 1;
-                w[0] = s1 ? (R)0 : w3[0];
-                w[1] = s1 ? w3[0] : w3[1];
-                w[2] = s1 ? w3[1] : w3[2];
-                w[3] = s1 ? w3[2] : (R)0;
-                if (sh != 0 && sh != 1) bad = true;
-            } else {
-                w[0] = w3[0];
-                w[1] = w3[1];
-                w[2] = w3[2];
-                if (sh != 0) bad = true;
-            }
-        }
-        const R fd = (R)(Fs[3 * p + D] * inv_h3);
-#pragma unroll
-        for (int z = 0; z < Dm::LZ; ++z) {
-            const R fz = fd * wz[z];
-#pragma unroll
-            for (int y = 0; y < Dm::LY; ++y) {
-                const R fzy = fz * wy[y];
-#pragma unroll
-                for (int x = 0; x < Dm::LX; ++x) acc[z][y][x] += fzy * wx[x];
-            }
-        }
-    }
-    // block origin in tile coordinates: point k - 1 is tile index k - kmin
-    const int ox = kc[0] - kmin[0], oy = kc[1] - kmin[1], oz = kc[2] - kmin[2];
-#pragma unroll
-    for (int z = 0; z < Dm::LZ; ++z)
-#pragma unroll
-        for (int y = 0; y < Dm::LY; ++y)
-#pragma unroll
-            for (int x = 0; x < Dm::LX; ++x) {
-                const int t = ((oz + z) * Ty + (oy + y)) * Tx + (ox + x);
-                if (acc[z][y][x] != (R)0 && t >= 0 && t < T) lds_add(tile + t, (double)acc[z][y][x]);
-            }
-}
-
-// Raw packed records (vector loads) and their fields.
-template <typename R>
-struct RawEdge;
-template <>
-struct RawEdge<double> {
-    int4 a, b;
-    __device__ static RawEdge load(const void *base, int t) {
-        const int4 *p = (const int4 *)base + 2 * (int64_t)t;
-        return {p[0], p[1]};
-    }
-    __device__ int4 ids() const {
-        return {a.x & 0xFFFF, (int)((unsigned)a.x >> 16), a.y & 0xFFFF, (int)((unsigned)a.y >> 16)};
-    }
-    __device__ double l0() const { return __hiloint2double(a.w, a.z); }
-    __device__ double c0() const { return __hiloint2double(b.y, b.x); }
-    __device__ double s0() const { return __hiloint2double(b.w, b.z); }
-};
-template <>
-struct RawEdge<float> {
-    int2 a, b, c;
-    __device__ static RawEdge load(const void *base, int t) {
-        const int2 *p = (const int2 *)base + 3 * (int64_t)t;
-        return {p[0], p[1], p[2]};
-    }
-    __device__ int4 ids() const {
-        return {a.x & 0xFFFF, (int)((unsigned)a.x >> 16), a.y & 0xFFFF, (int)((unsigned)a.y >> 16)};
-    }
-    __device__ float l0() const { return __int_as_float(b.x); }
-    __device__ float c0() const { return __int_as_float(b.y); }
-    __device__ float s0() const { return __int_as_float(c.x); }
-};
-__device__ __forceinline__ double face_a0(const int4 &r, double) { return __hiloint2double(r.w, r.z); }
-__device__ __forceinline__ float face_a0(const int4 &r, float) { return __int_as_float(r.z); }
 
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
@@ -320,7 +83,6 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     double *xs = (double *)lds;                       // [nmax][3]
     double *Fs = xs + 3 * a.nmax;                     // [nmax][3]
     unsigned char *tile_region = (unsigned char *)(Fs + 3 * a.nmax);
-    int *hist = (int *)tile_region;                   // P3: cell counts, then flags
     double *ftile = (double *)tile_region;            // P4: force tile (FP64)
     R *utile = (R *)tile_region;                      // P5: velocity tile
     uint16_t *occ_start = (uint16_t *)(tile_region + a.tile_bytes);  // [nmax] first node
@@ -349,39 +111,11 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
         }
     }
 
-    // ---- P0: positions (contiguous for a whole body, gathered for a patch) ----
-    if (whole) {
-        copy_to_lds<NT>(xs, a.X + 3 * n0, 3 * NL);
-    } else {
-        for (int i = tid; i < NL; i += NT) {
-            const int64_t g = gid[i];
-            xs[3 * i] = a.X[3 * g];
-            xs[3 * i + 1] = a.X[3 * g + 1];
-            xs[3 * i + 2] = a.X[3 * g + 2];
-        }
-    }
+    // ---- P0: positions (contiguous for a whole body, gathered for a patch),
+    // cell bounding box of the owned nodes (the ones spread and interpolated) ----
     for (int i = tid; i < 3 * NL; i += NT) Fs[i] = 0.0;
-    __syncthreads();
-    // cell bounding box of the owned nodes (the ones spread and interpolated)
-    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-#pragma unroll
-    for (int s = 0; s < K; ++s) {
-        const int j = tid + s * NT;
-        if (j < N) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int kc = cell_of(xs[3 * j + c], a.inv_h);
-                lo[c] = min(lo[c], kc);
-                hi[c] = max(hi[c], kc);
-            }
-        }
-    }
     int kmin[3], kmax[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        kmin[c] = block_min_int<NT>(lo[c], ired);
-        kmax[c] = block_max_int<NT>(hi[c], ired);
-    }
+    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, ired, kmin, kmax);
 
     // ---- P1: volume and area (a whole body; a patched body's come from the
     // geometry pass that precedes this kernel) ----
@@ -470,154 +204,18 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     __syncthreads();
 
     // ---- P3: counting sort by cell; permute xs and Fs into cell order ----
-    const int Cx = kmax[0] - kmin[0] + 1, Cy = kmax[1] - kmin[1] + 1, Cz = kmax[2] - kmin[2] + 1;
-    const int Tx = Cx + 3, Ty = Cy + 3, Tz = Cz + 3;    // points kmin-1 .. kmax+2
-    const long long Cl = (long long)Cx * Cy * Cz, Tl = (long long)Tx * Ty * Tz;
-    const bool use_tile = Cx >= 1 && Cy >= 1 && Cz >= 1 && Cl <= 65535 && Cl * 8 <= a.tile_bytes &&
-                          Tl * 8 <= a.tile_bytes;
-    const int C = use_tile ? (int)Cl : 0, T = use_tile ? (int)Tl : 0;
     int pos[K];
-#pragma unroll
-    for (int s = 0; s < K; ++s) pos[s] = tid + s * NT;     // identity unless sorted
-    if (use_tile) {
-        for (int c = tid; c < C; c += NT) hist[c] = 0;
-        __syncthreads();
-        int key[K];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int j = tid + s * NT;
-            key[s] = 0;
-            if (j < N) {
-                key[s] = ((cell_of(xs[3 * j + 2], a.inv_h) - kmin[2]) * Cy +
-                          (cell_of(xs[3 * j + 1], a.inv_h) - kmin[1])) * Cx +
-                         (cell_of(xs[3 * j], a.inv_h) - kmin[0]);
-                atomicAdd(hist + key[s], 1);
-            }
-        }
-        __syncthreads();
-        int *occ_idx = hist + C;
-        for (int c = tid; c < C; c += NT) occ_idx[c] = hist[c] > 0 ? 1 : 0;
-        __syncthreads();
-        const int n_occ = block_exclusive_scan<NT>(occ_idx, C, ired);
-        block_exclusive_scan<NT>(hist, C, ired);
-        for (int c = tid; c < C; c += NT) {
-            const int start = hist[c];
-            const int next = c + 1 < C ? hist[c + 1] : N;
-            if (next > start) {
-                occ_start[occ_idx[c]] = (uint16_t)start;
-                occ_cnt[occ_idx[c]] = (uint16_t)(next - start);
-            }
-        }
-        if (tid == 0) n_occ_sh = n_occ;
-        if (tid <= kCountBins) cnt_bins[tid] = 0;
-        __syncthreads();
-        // order the occupied cells by decreasing node count, so that the
-        // threads of a wave spread cells of similar size (counting sort)
-        int ost[K], ocn[K], obin[K];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int o = tid + s * NT;
-            ost[s] = o < n_occ ? occ_start[o] : 0;
-            ocn[s] = o < n_occ ? occ_cnt[o] : 0;
-            obin[s] = kCountBins - min(ocn[s], kCountBins);
-            if (o < n_occ) atomicAdd(cnt_bins + obin[s], 1);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int run = 0;
-            for (int i = 0; i <= kCountBins; ++i) {
-                const int v = cnt_bins[i];
-                cnt_bins[i] = run;
-                run += v;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int o = tid + s * NT;
-            if (o < n_occ) {
-                const int r = atomicAdd(cnt_bins + obin[s], 1);
-                occ_start[r] = (uint16_t)ost[s];
-                occ_cnt[r] = (uint16_t)ocn[s];
-            }
-        }
-        double xr[K][3], fr[K][3];
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int j = tid + s * NT;
-            if (j < N) {
-                pos[s] = atomicAdd(hist + key[s], 1);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xr[s][c] = xs[3 * j + c];
-                    fr[s][c] = Fs[3 * j + c];
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            const int j = tid + s * NT;
-            if (j < N) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xs[3 * pos[s] + c] = xr[s][c];
-                    Fs[3 * pos[s] + c] = fr[s][c];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    const TileGeom tg{{kmin[0], kmin[1], kmin[2]}, Tx, Ty, Tz, T, a.nx, a.ny, a.nz, a.plane};
+    const CellSort cs = cell_sort<NT>(xs, Fs, N, kmin, kmax, a.inv_h, tile_region, a.tile_bytes,
+                                      occ_start, occ_cnt, ired, &n_occ_sh, cnt_bins, pos, a.nx,
+                                      a.ny, a.nz, a.plane);
+    const bool use_tile = cs.use_tile;
+    const TileGeom &tg = cs.tg;
+    const int Tx = tg.Tx, Ty = tg.Ty, Tz = tg.Tz;
 
     // ---- P4: spreading ----
-    if (a.f != nullptr) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            R *fd = (R *)a.f + d * a.field;
-            if (use_tile) {
-                for (int t = tid; t < T; t += NT) ftile[t] = 0.0;
-                __syncthreads();
-                const int n_occ = n_occ_sh;
-                for (int o = tid; o < n_occ; o += NT) {
-                    const int p = occ_start[o], q = p + occ_cnt[o];
-                    const int kcell[3] = {cell_of(xs[3 * p], a.inv_h), cell_of(xs[3 * p + 1], a.inv_h),
-                                          cell_of(xs[3 * p + 2], a.inv_h)};
-                    if (d == 0)
-                        spread_cell<R, 0>(xs, Fs, p, q, kcell, kmin, Tx, Ty, T, a.inv_h, a.inv_h3,
-                                          ftile, bad);
-                    else if (d == 1)
-                        spread_cell<R, 1>(xs, Fs, p, q, kcell, kmin, Tx, Ty, T, a.inv_h, a.inv_h3,
-                                          ftile, bad);
-                    else
-                        spread_cell<R, 2>(xs, Fs, p, q, kcell, kmin, Tx, Ty, T, a.inv_h, a.inv_h3,
-                                          ftile, bad);
-                }
-                __syncthreads();
-                for (int t = tid; t < T; t += NT) {
-                    const double v = ftile[t];
-                    if (v != 0.0) unsafeAtomicAdd(fd + tg.grid_index(t), (R)v);
-                }
-                __syncthreads();
-            } else {
-                for (int p = tid; p < N; p += NT) {
-                    R wx[3], wy[3], wz[3];
-                    const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
-                    const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
-                    const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
-                    const R fv = (R)(Fs[3 * p + d] * a.inv_h3);
-                    for (int z = 0; z < 3; ++z)
-                        for (int y = 0; y < 3; ++y) {
-                            R *row = fd + wrapi(cz - 1 + z, a.nz) * a.plane +
-                                     (int64_t)wrapi(cy - 1 + y, a.ny) * a.nx;
-                            const R fzy = fv * wz[z] * wy[y];
-                            for (int x = 0; x < 3; ++x)
-                                unsafeAtomicAdd(row + wrapi(cx - 1 + x, a.nx), fzy * wx[x]);
-                        }
-                }
-            }
-        }
-    }
+    if (a.f != nullptr)
+        spread_to_grid<R, NT>(xs, Fs, N, cs, occ_start, occ_cnt, ftile, (R *)a.f, a.field, a.inv_h,
+                              a.inv_h3, bad);
 
     // ---- P5: interpolation and update, one lattice (= one component) at a time ----
     // Nodes are visited in work order (cell order when sorted); the new
@@ -746,8 +344,8 @@ void pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s) {
                            (const R *)ref->A0, (FaceRec<R> *)p->face_rec);
 }
 
-// New positions of patched bodies: staging array -> X (owned nodes of each
-// patch unit; one workgroup per unit).
+// Results of patched bodies: staging array -> destination (owned nodes of
+// each patch unit; one workgroup per unit).
 __global__ void k_commit(const int32_t *__restrict__ units, const int64_t *__restrict__ noff,
                          const int32_t *__restrict__ owned, const int32_t *__restrict__ nodes,
                          const double *__restrict__ Xstage, double *__restrict__ X) {
@@ -762,6 +360,14 @@ __global__ void k_commit(const int32_t *__restrict__ units, const int64_t *__res
 }
 
 }  // namespace
+
+ip_status launch_commit(ip_plan *p, const double *src, double *dst, hipStream_t s) {
+    if (p->n_patched_units == 0) return IP_OK;
+    hipLaunchKernelGGL(k_commit, dim3(p->n_patched_units), dim3(256), 0, s, p->patched_units,
+                       p->wu_noff, p->wu_owned, p->wu_nodes, src, dst);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
 
 ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s) {
     if (p->prec == IP_F64)

@@ -30,6 +30,9 @@ CASES = {
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
                                          cells_per_unit=64),
+    # a shell split into patches by the fused reverse step
+    "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
+                                           cells_per_unit=96),
 }
 
 
@@ -104,10 +107,10 @@ def test_step_vjp_parity(case):
     e_gu = rel_inf(host(gu), want_gu)
     say(f"  lam {e_lam:.2e}  gk {e_gk:.2e}  gu {e_gu:.2e}")
     assert e_lam <= TOL and e_gk <= 1e-11 and e_gu <= TOL
-    # the adjoint may be updated in place
+    # the adjoint may be updated in place (same result up to summation order)
     lam_in = dev(lam1)
     N.ip_step_vjp(plan, dev(wl.X), gref, k, dev(u), dt, lam_in, lam=lam_in)
-    assert np.array_equal(host(lam_in), host(lam))
+    assert per_body_rel(host(lam_in) - lam1, want_lam - lam1, wl.node_off) <= TOL
 
 
 @pytest.mark.parametrize("case", ["drop_L3_64", "four_L2_32", "uneven_small"])
@@ -126,7 +129,7 @@ def test_taylor_parity(case):
     assert err <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["four_L2_32", "ventricle_small"])
+@pytest.mark.parametrize("case", ["four_L2_32", "ventricle_small", "ventricle_patched"])
 def test_rollout_gradients(case):
     """Three explicit steps, loss = sum_b (D_b - D*_b)^2 on the final
     positions, gradients with respect to X0, the constants and u."""
