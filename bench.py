@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
-KERNEL_SOURCES = ["paper_1612_03399_amd/csrc/k_step.hip", "paper_1612_03399_amd/csrc/elements.h",
+KERNEL_SOURCES = ["paper_1612_03399_amd/csrc/k_step.hip", "paper_1612_03399_amd/csrc/step_common.h",
+                  "paper_1612_03399_amd/csrc/elements.h",
                   "paper_1612_03399_amd/csrc/ipibm_internal.h",
                   "paper_1612_03399_amd/csrc/workunits.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fused_{workload}_{dtype}.json")
@@ -74,7 +75,7 @@ def algorithmic_bytes(wl, touched, real_bytes):
     return nodes + edges + faces + bodies + grid
 
 
-def load_traffic(workload, dtype, options):
+def load_traffic(workload, dtype, launch):
     """Measured HBM bytes per launch from the committed counter summary, when it
     was taken on the current kernel sources and launch shape (else None)."""
     path = TRAFFIC_FILE.format(workload=workload, dtype=dtype)
@@ -84,8 +85,8 @@ def load_traffic(workload, dtype, options):
         t = json.load(fh)
     if t.get("source_hash") != kernel_source_hash():
         return None, "stale (kernel changed since the counters were taken)"
-    if t.get("options", {}) != options:
-        return None, f"taken with launch options {t.get('options', {})}, not {options}"
+    if t.get("launch") != launch:
+        return None, f"taken with launch shape {t.get('launch')}, not {launch}"
     return t["bytes_per_launch"], os.path.relpath(path, ROOT)
 
 
@@ -134,7 +135,8 @@ def backward_leg(N, W, bodies, dev, torch, log, steps=10, reps=3):
     wl = W.config4(n_bodies=bodies)
     u = torch.as_tensor(wl.velocity(dtype=np.float64)).to(dev)
     plan = N.Plan(wl, wl.grid, "f64")
-    ref = N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev))
+    N.ip_plan_bind_reference(plan, N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev)))
+    ref = None            # the bound reference (packed once)
     km = torch.as_tensor(np.stack([wl.ks, wl.kb, wl.kA, wl.kV])).to(dev)
     mass = torch.as_tensor(np.asarray(wl.mass, np.float64)).to(dev)
     Ds = torch.as_tensor(wl.targets).to(dev)
@@ -261,6 +263,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other-precision, graph, differentiation and uneven legs")
+    ap.add_argument("--legs", default="other,backward,uneven",
+                    help="extra legs to run: other (other precision + hipGraph), backward, uneven")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -334,7 +338,8 @@ def main():
     bytes_step = algorithmic_bytes(wl, touched, real_bytes)
     gbs = bytes_step / (ms * 1e-3) / 1e9
     value = wl.n_nodes / (ms * 1e-3)
-    traffic, traffic_src = load_traffic(wl.name, args.precision, options)
+    launch = {"threads": plan.step_threads, "tile_bytes": plan.tile_bytes, "units": plan.n_units}
+    traffic, traffic_src = load_traffic(wl.name, args.precision, launch)
     kernel = (f"k_step_fused<{'double' if args.precision == 'f64' else 'float'}, "
               f"{plan.step_threads}>") if plan.fused else "unfused step"
     if plan.patched_bodies:
@@ -365,8 +370,10 @@ def main():
     del plan, X, u, f
     torch.cuda.empty_cache()
 
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(args.legs.split(","))
+    if legs:
         extras = {}
+    if "other" in legs:
         other = "f32" if args.precision == "f64" else "f64"
         plan2, ref2, k2, X2, u2, f2, V2, A2 = setup(other)
         ms2 = time_steps(N, plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, args.steps,
@@ -400,10 +407,12 @@ def main():
         log(f"{other} graph replay: {extras[f'{other}_graph_ms_per_step']:.4f} ms/step")
         del g, plan2, X2, u2, f2
         torch.cuda.empty_cache()
-        if args.precision == "f64":
-            extras.update(backward_leg(N, W, args.bodies, dev, torch, log))
+    if "backward" in legs and args.precision == "f64":
+        extras.update(backward_leg(N, W, args.bodies, dev, torch, log))
         torch.cuda.empty_cache()
+    if "uneven" in legs:
         extras.update(uneven_leg(N, W, dev, torch, log))
+    if legs:
         out["extras"] = extras
 
     if not args.no_cpu_baseline:
