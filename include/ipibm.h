@@ -243,8 +243,11 @@ ip_status ip_forces_jvp(ip_plan *plan, const double *X, const double *dX,
  *   gu       += dt h^3 spread(P)   (double[3][nz][ny][nx], may be NULL; the
  *               adjoint of interpolation is spreading).
  * X is the position at which the forward step was taken (a checkpoint).
- * lam may alias lam_next.  The first call allocates a workspace of
- * 16 (E + F) bytes; later calls allocate nothing. */
+ * lam may alias lam_next.  On plans with a fused step (ip_plan_properties
+ * props[0] = 1) this runs as one fused kernel per work unit over the same
+ * packed element records (accumulations in a run-dependent order) and
+ * allocates nothing; otherwise the first call allocates a workspace of
+ * 16 (E + F) bytes and the element kernels run separately. */
 ip_status ip_step_vjp(ip_plan *plan, const double *X, const ip_reference *ref,
                       const ip_constants *k, const double *u, double dt, const double *lam_next,
                       double *lam, double *gk, double *gu, void *stream);
