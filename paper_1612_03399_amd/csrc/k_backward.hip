@@ -437,9 +437,8 @@ struct VjpArgs {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ double red[NT / 64];
-    __shared__ int ired[NT / 64];
-    __shared__ double bcd[2];
+    __shared__ double red[4 * (NT / 64)];
+    __shared__ int ired[6 * (NT / 64)];
     __shared__ int n_occ_sh;
     __shared__ int cnt_bins[kCountBins + 1];
 
@@ -503,13 +502,12 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
     // ---- P0 ----
     for (int i = tid; i < 3 * NL; i += NT) dF[i] = 0.0;
     int kmin[3], kmax[3];
-    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, ired, kmin, kmax);
+    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, kmin, kmax);
 
-    // ---- P1: V and dV ----
-    double Vb, dVb;
+    // ---- P1: V and dV, reduced together with the bounding box ----
+    double sums[2] = {0.0, 0.0};
     if (whole) {
         const vec3<dual> anchor = dualx(0, tangent(0));
-        double v6 = 0.0, dv6 = 0.0;
 #pragma unroll
         for (int s = 0; s < FK; ++s) {
             if (fmask & (1u << s)) {
@@ -518,19 +516,16 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
                 face_geometry<dual, double>(dualx(fi[s][0], tangent(fi[s][0])),
                                             dualx(fi[s][1], tangent(fi[s][1])),
                                             dualx(fi[s][2], tangent(fi[s][2])), anchor, v, ar);
-                v6 += v.v;
-                dv6 += v.d;
+                sums[0] += v.v;
+                sums[1] += v.d;
             }
         }
-        v6 = block_sum(v6, red);
-        dv6 = block_sum(dv6, red);
-        if (tid == 0) {
-            bcd[0] = v6 * (1.0 / 6.0);
-            bcd[1] = dv6 * (1.0 / 6.0);
-        }
-        __syncthreads();
-        Vb = bcd[0];
-        dVb = bcd[1];
+    }
+    block_box_sums<NT, 2>(kmin, kmax, sums, ired, red);
+    double Vb, dVb;
+    if (whole) {
+        Vb = sums[0] * (1.0 / 6.0);
+        dVb = sums[1] * (1.0 / 6.0);
     } else {
         Vb = a.Vpre[b];
         dVb = a.dVpre[b];
@@ -594,17 +589,12 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
             }
         }
     }
-    dot_s = block_sum(dot_s, red);
-    dot_b = block_sum(dot_b, red);
-    dot_a = block_sum(dot_a, red);
-    dot_v = block_sum(dot_v, red);
+    double dots[4] = {dot_s, dot_b, dot_a, dot_v};
+    block_sums<NT, 4>(dots, red);      // its barriers also complete dF
     if (tid == 0 && a.gk) {
-        atomicAdd(a.gk + b, c2 * dot_s);
-        atomicAdd(a.gk + a.B + b, c2 * dot_b);
-        atomicAdd(a.gk + 2 * a.B + b, c2 * dot_a);
-        atomicAdd(a.gk + 3 * a.B + b, c2 * dot_v);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) atomicAdd(a.gk + f * a.B + b, c2 * dots[f]);
     }
-    __syncthreads();      // dF complete
 
     // ---- P2b + P3: lam = lam' + dt^2/m dF written for the owned nodes, and
     // their dF replaced in place by P' = dt h^3 P (each thread its own nodes).
@@ -633,24 +623,40 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
                                       a.ny, a.nz, a.plane);
     const TileGeom &tg = cs.tg;
 
-    // ---- P4: gu += spread(P') ----
+    // ---- P4: gu += spread(P'); the velocity tile of lattice 0 is fetched
+    // into registers before the last flush ----
+    constexpr int PF = NT >= 768 ? 5 : 8;
+    TilePrefetch<NT, double, PF> pf;
+    const bool pf_ok = cs.use_tile && TilePrefetch<NT, double, PF>::covers(tg);
+    bool have0 = false;
     if (a.gu != nullptr)
         spread_to_grid<double, NT>(xs, dF, N, cs, occ_start, occ_cnt, ftile, a.gu, a.field,
-                                   a.inv_h, a.inv_h3, bad);
+                                   a.inv_h, a.inv_h3, bad, [&] {
+                                       if (pf_ok) {
+                                           pf.load(a.u, tg);
+                                           have0 = true;
+                                       }
+                                   });
 
-    // ---- P5: J_U^T P' per owned node, one lattice at a time ----
+    // ---- P5: J_U^T P' per owned node, one lattice at a time; the velocity
+    // tile of lattice d + 1 is loaded into registers while lattice d is used ----
     double gacc[K][3];
 #pragma unroll
     for (int s = 0; s < K; ++s)
 #pragma unroll
         for (int c = 0; c < 3; ++c) gacc[s][c] = 0.0;
-    __syncthreads();
+    if (pf_ok && !have0) pf.load(a.u, tg);
+    lds_barrier();
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double *ud = a.u + d * a.field;
         if (cs.use_tile) {
-            stage_tile<NT>(utile, ud, tg);
-            __syncthreads();
+            if (pf_ok)
+                pf.store(utile, tg);
+            else
+                stage_tile<NT>(utile, ud, tg);
+            lds_barrier();
+            if (pf_ok && d < 2) pf.load(ud + a.field, tg);
         }
 #pragma unroll
         for (int s = 0; s < K; ++s) {
@@ -704,7 +710,7 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
             gacc[s][1] += pd * gy;
             gacc[s][2] += pd * gz;
         }
-        if (cs.use_tile) __syncthreads();
+        if (cs.use_tile) lds_barrier();
     }
 #pragma unroll
     for (int s = 0; s < K; ++s) {

@@ -53,9 +53,8 @@ struct StepArgs {
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ double red[NT / 64];
-    __shared__ int ired[NT / 64];
-    __shared__ double bcd[1];
+    __shared__ double red[2 * (NT / 64)];
+    __shared__ int ired[6 * (NT / 64)];
     __shared__ int n_occ_sh;
     __shared__ int cnt_bins[kCountBins + 1];
 
@@ -112,36 +111,37 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     }
 
     // ---- P0: positions (contiguous for a whole body, gathered for a patch),
-    // cell bounding box of the owned nodes (the ones spread and interpolated) ----
+    // this thread's share of the cell bounding box of the owned nodes (the
+    // ones spread and interpolated) ----
     for (int i = tid; i < 3 * NL; i += NT) Fs[i] = 0.0;
     int kmin[3], kmax[3];
-    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, ired, kmin, kmax);
+    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, kmin, kmax);
 
     // ---- P1: volume and area (a whole body; a patched body's come from the
-    // geometry pass that precedes this kernel) ----
-    double Vb;
+    // geometry pass that precedes this kernel), reduced together with the
+    // bounding box ----
+    double sums[2] = {0.0, 0.0};
     if (whole) {
         const vec3<double> anchor = ldx(xs, 0);
-        double v6 = 0.0, a2 = 0.0;
 #pragma unroll
         for (int s = 0; s < FK; ++s) {
             if (fmask & (1u << s)) {
                 double v, ar;
                 face_geometry<double, R>(ldx(xs, fi[s][0]), ldx(xs, fi[s][1]), ldx(xs, fi[s][2]),
                                          anchor, v, ar);
-                v6 += v;
-                a2 += ar;
+                sums[0] += v;
+                sums[1] += ar;
             }
         }
-        v6 = block_sum(v6, red);
-        a2 = block_sum(a2, red);
+    }
+    block_box_sums<NT, 2>(kmin, kmax, sums, ired, red);
+    double Vb;
+    if (whole) {
+        Vb = sums[0] * (1.0 / 6.0);
         if (tid == 0) {
-            bcd[0] = v6 * (1.0 / 6.0);
-            a.V[b] = bcd[0];
-            a.A[b] = 0.5 * a2;
+            a.V[b] = Vb;
+            a.A[b] = 0.5 * sums[1];
         }
-        __syncthreads();
-        Vb = bcd[0];
     } else {
         Vb = a.V[b];
     }
@@ -212,22 +212,39 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     const TileGeom &tg = cs.tg;
     const int Tx = tg.Tx, Ty = tg.Ty, Tz = tg.Tz;
 
-    // ---- P4: spreading ----
+    // ---- P4: spreading; the velocity tile of lattice 0 is fetched into
+    // registers before the last flush ----
+    constexpr int PF = NT >= 768 ? 5 : 8;
+    TilePrefetch<NT, R, PF> pf;
+    const bool pf_ok = use_tile && TilePrefetch<NT, R, PF>::covers(tg);
+    bool have0 = false;
     if (a.f != nullptr)
         spread_to_grid<R, NT>(xs, Fs, N, cs, occ_start, occ_cnt, ftile, (R *)a.f, a.field, a.inv_h,
-                              a.inv_h3, bad);
+                              a.inv_h3, bad, [&] {
+                                  if (pf_ok) {
+                                      pf.load((const R *)a.u, tg);
+                                      have0 = true;
+                                  }
+                              });
 
     // ---- P5: interpolation and update, one lattice (= one component) at a time ----
     // Nodes are visited in work order (cell order when sorted); the new
     // coordinate d replaces F_d in Fs, which nothing reads after this lattice.
+    // The velocity tile of lattice d + 1 is loaded into registers while
+    // lattice d is interpolated.
     const double cm = a.dt * a.dt / a.mass[b];
-    __syncthreads();      // every thread is done with spreading
+    if (pf_ok && !have0) pf.load((const R *)a.u, tg);
+    lds_barrier();      // every thread is done with spreading
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const R *ud = (const R *)a.u + d * a.field;
         if (use_tile) {
-            stage_tile<NT>(utile, ud, tg);
-            __syncthreads();
+            if (pf_ok)
+                pf.store(utile, tg);
+            else
+                stage_tile<NT>(utile, ud, tg);
+            lds_barrier();
+            if (pf_ok && d < 2) pf.load(ud + a.field, tg);
         }
         for (int p = tid; p < N; p += NT) {
             R wx[3], wy[3], wz[3];
@@ -265,7 +282,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
             if (!isfinite(fd) || !isfinite((double)acc)) atomicOr(a.status, IP_STATUS_NONFINITE);
             Fs[3 * p + d] = xd + a.dt * (double)acc + cm * (double)(R)fd;
         }
-        if (use_tile) __syncthreads();
+        if (use_tile) lds_barrier();
     }
     __syncthreads();
     // back to node order (pinned nodes keep their position), staged in xs;

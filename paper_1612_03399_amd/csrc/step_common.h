@@ -22,6 +22,25 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Values equal in every lane, moved to scalar registers (the compiler cannot
+// see that a value reduced over the block is uniform).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Workgroup barrier that orders LDS accesses only: outstanding global memory
+// operations (the grid atomics of a tile flush, prefetch loads) stay in
+// flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ vec3<double> ldx(const double *xs, int i) {
     return {xs[3 * i], xs[3 * i + 1], xs[3 * i + 2]};
 }
@@ -59,6 +78,85 @@ template <int NT>
 __device__ __forceinline__ int block_min_int(int v, int *sh) { return block_extreme_int<NT, false>(v, sh); }
 template <int NT>
 __device__ __forceinline__ int block_max_int(int v, int *sh) { return block_extreme_int<NT, true>(v, sh); }
+
+// The cell bounding box of a unit (minimum of lo[3], maximum of hi[3]) and D
+// double sums s[D], reduced over the block in one pass (two barriers); every
+// thread receives every result, the sums added in a fixed order.  ish holds
+// 6 NT/64 ints, dsh D NT/64 doubles.
+template <int NT, int D>
+__device__ __forceinline__ void block_box_sums(int lo[3], int hi[3], double s[D], int *ish,
+                                               double *dsh) {
+    constexpr int W = NT / 64;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], __shfl_xor(lo[c], o, 64));
+            hi[c] = max(hi[c], __shfl_xor(hi[c], o, 64));
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) s[j] += __shfl_xor(s[j], o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ish[6 * w + c] = lo[c];
+            ish[6 * w + 3 + c] = hi[c];
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) dsh[D * w + j] = s[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = ish[c];
+        hi[c] = ish[3 + c];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) s[j] = dsh[j];
+    for (int v = 1; v < W; ++v) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], ish[6 * v + c]);
+            hi[c] = max(hi[c], ish[6 * v + 3 + c]);
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) s[j] += dsh[D * v + j];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = uniform(lo[c]);
+        hi[c] = uniform(hi[c]);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) s[j] = uniform(s[j]);
+}
+
+// D double sums over the block in one pass (two barriers); every thread
+// receives them, added in a fixed order.  dsh holds D NT/64 doubles.
+template <int NT, int D>
+__device__ __forceinline__ void block_sums(double s[D], double *dsh) {
+    constexpr int W = NT / 64;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int j = 0; j < D; ++j) s[j] += __shfl_xor(s[j], o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < D; ++j) dsh[D * w + j] = s[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < D; ++j) s[j] = dsh[j];
+    for (int v = 1; v < W; ++v)
+#pragma unroll
+        for (int j = 0; j < D; ++j) s[j] += dsh[D * v + j];
+#pragma unroll
+    for (int j = 0; j < D; ++j) s[j] = uniform(s[j]);
+}
 
 // In-place exclusive scan of a[0..n) by the whole block; returns the total.
 template <int NT>
@@ -110,15 +208,48 @@ __device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__rest
     }
 }
 
+// The grid tile of a unit: points kmin-1 .. kmax+2 per axis, t = (z Ty + y) Tx
+// + x.  Threads walk it as t = threadIdx.x + k NT; each keeps its point's tile
+// coordinates and advances them by the step NT (s, in tile coordinates) with
+// at most one carry per axis, so no point needs a division.  The tile is no
+// larger than the grid along any axis, so a coordinate g0 + x wraps at most
+// once.
 struct TileGeom {
     int kmin[3];            // lowest occupied cell per axis
-    int Tx, Ty, Tz, T;      // the tile spans points kmin-1 .. kmax+2
+    int Tx, Ty, Tz, T;
     int nx, ny, nz;
     int64_t plane;
-    __device__ __forceinline__ int64_t grid_index(int t) const {
-        const int tx = t % Tx, ty = (t / Tx) % Ty, tz = t / (Tx * Ty);
-        return wrapi(kmin[2] - 1 + tz, nz) * plane + (int64_t)wrapi(kmin[1] - 1 + ty, ny) * nx +
-               wrapi(kmin[0] - 1 + tx, nx);
+    int g0[3];              // wrapped grid coordinates of tile point 0
+    int s[3];               // NT in tile coordinates (s[0] < Tx, s[1] < Ty)
+    int c0[3];              // this thread's first point
+};
+
+struct TileCursor {
+    int t, x, y, z;
+    __device__ __forceinline__ static TileCursor first(const TileGeom &g) {
+        return {(int)threadIdx.x, g.c0[0], g.c0[1], g.c0[2]};
+    }
+    template <int NT>
+    __device__ __forceinline__ void next(const TileGeom &g) {
+        t += NT;
+        x += g.s[0];
+        y += g.s[1];
+        z += g.s[2];
+        if (x >= g.Tx) {
+            x -= g.Tx;
+            ++y;
+        }
+        if (y >= g.Ty) {
+            y -= g.Ty;
+            ++z;
+        }
+    }
+    __device__ __forceinline__ int64_t grid_index(const TileGeom &g) const {
+        int gx = g.g0[0] + x, gy = g.g0[1] + y, gz = g.g0[2] + z;
+        gx -= gx >= g.nx ? g.nx : 0;
+        gy -= gy >= g.ny ? g.ny : 0;
+        gz -= gz >= g.nz ? g.nz : 0;
+        return (int64_t)gz * g.plane + (int64_t)gy * g.nx + gx;
     }
 };
 
@@ -126,20 +257,45 @@ struct TileGeom {
 template <int NT, typename R, int U = 8>
 __device__ __forceinline__ void stage_tile(R *__restrict__ tile, const R *__restrict__ field,
                                            const TileGeom &g) {
-    for (int base = 0; base < g.T; base += NT * U) {
+    TileCursor c = TileCursor::first(g);
+    while (c.t < g.T) {
         R v[U];
+        int t[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const int t = base + k * NT + (int)threadIdx.x;
-            v[k] = t < g.T ? field[g.grid_index(t)] : (R)0;
+            t[k] = c.t;
+            v[k] = c.t < g.T ? field[c.grid_index(g)] : (R)0;
+            c.template next<NT>(g);
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int t = base + k * NT + (int)threadIdx.x;
+        for (int k = 0; k < U; ++k)
+            if (t[k] < g.T) tile[t[k]] = v[k];
+    }
+}
+
+// A grid tile held in registers, PF values per thread: loaded while the
+// previous tile is in use (the loads stay in flight), stored to LDS once that
+// tile is free.  Covers tiles of at most PF NT points.
+template <int NT, typename R, int PF>
+struct TilePrefetch {
+    R v[PF];
+    __device__ __forceinline__ static bool covers(const TileGeom &g) { return g.T <= PF * NT; }
+    __device__ __forceinline__ void load(const R *__restrict__ field, const TileGeom &g) {
+        TileCursor c = TileCursor::first(g);
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            v[k] = c.t < g.T ? field[c.grid_index(g)] : (R)0;
+            c.template next<NT>(g);
+        }
+    }
+    __device__ __forceinline__ void store(R *__restrict__ tile, const TileGeom &g) const {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int t = (int)threadIdx.x + k * NT;
             if (t < g.T) tile[t] = v[k];
         }
     }
-}
+};
 
 template <int D>
 struct BlockDims {
@@ -250,12 +406,13 @@ __device__ __forceinline__ float face_a0(const int4 &r, float) { return __int_as
 
 // ---------------------------------------------------------------------------
 // Unit positions -> LDS (contiguous for a whole body, gathered for a patch),
-// and the cell bounding box of the first N (owned) nodes.
+// and this thread's share of the cell bounding box of the first N (owned)
+// nodes (lo, hi: to be reduced over the block with block_box_sums).
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ void load_positions(double *xs, const double *X, bool whole, int64_t n0,
                                                const int32_t *gid, int NL, int N, double inv_h,
-                                               int *ired, int kmin[3], int kmax[3]) {
+                                               int lo[3], int hi[3]) {
     const int tid = threadIdx.x;
     if (whole) {
         copy_to_lds<NT>(xs, X + 3 * n0, 3 * NL);
@@ -268,7 +425,11 @@ __device__ __forceinline__ void load_positions(double *xs, const double *X, bool
         }
     }
     __syncthreads();
-    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = INT_MAX;
+        hi[c] = INT_MIN;
+    }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         const int j = tid + s * NT;
@@ -280,11 +441,6 @@ __device__ __forceinline__ void load_positions(double *xs, const double *X, bool
                 hi[c] = max(hi[c], kc);
             }
         }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        kmin[c] = block_min_int<NT>(lo[c], ired);
-        kmax[c] = block_max_int<NT>(hi[c], ired);
     }
 }
 
@@ -314,7 +470,7 @@ __device__ CellSort cell_sort(double *xs, double *vals, int N, const int kmin[3]
     const int Tx = Cx + 3, Ty = Cy + 3, Tz = Cz + 3;    // points kmin-1 .. kmax+2
     const long long Cl = (long long)Cx * Cy * Cz, Tl = (long long)Tx * Ty * Tz;
     const bool use_tile = Cx >= 1 && Cy >= 1 && Cz >= 1 && Cl <= 65535 && Cl * 8 <= tile_bytes &&
-                          Tl * 8 <= tile_bytes;
+                          Tl * 8 <= tile_bytes && Tx <= nx && Ty <= ny && Tz <= nz;
     const int C = use_tile ? (int)Cl : 0, T = use_tile ? (int)Tl : 0;
 #pragma unroll
     for (int s = 0; s < K; ++s) pos[s] = tid + s * NT;     // identity unless sorted
@@ -338,7 +494,7 @@ __device__ CellSort cell_sort(double *xs, double *vals, int N, const int kmin[3]
         int *occ_idx = hist + C;
         for (int c = tid; c < C; c += NT) occ_idx[c] = hist[c] > 0 ? 1 : 0;
         __syncthreads();
-        n_occ = block_exclusive_scan<NT>(occ_idx, C, ired);
+        n_occ = uniform(block_exclusive_scan<NT>(occ_idx, C, ired));
         block_exclusive_scan<NT>(hist, C, ired);
         for (int c = tid; c < C; c += NT) {
             const int start = hist[c];
@@ -406,7 +562,21 @@ __device__ CellSort cell_sort(double *xs, double *vals, int N, const int kmin[3]
         }
         __syncthreads();
     }
-    return {use_tile, C, n_occ, TileGeom{{kmin[0], kmin[1], kmin[2]}, Tx, Ty, Tz, T, nx, ny, nz, plane}};
+    TileGeom tg{{kmin[0], kmin[1], kmin[2]}, Tx, Ty, Tz, T, nx, ny, nz, plane, {0, 0, 0}, {0, 0, 0},
+                {0, 0, 0}};
+    if (use_tile) {
+        tg.g0[0] = wrapi(kmin[0] - 1, nx);
+        tg.g0[1] = wrapi(kmin[1] - 1, ny);
+        tg.g0[2] = wrapi(kmin[2] - 1, nz);
+        const int q = NT / Tx, r = tid / Tx;
+        tg.s[0] = NT % Tx;
+        tg.s[1] = q % Ty;
+        tg.s[2] = q / Ty;
+        tg.c0[0] = tid % Tx;
+        tg.c0[1] = r % Ty;
+        tg.c0[2] = r / Ty;
+    }
+    return {use_tile, C, n_occ, tg};
 }
 
 // ---------------------------------------------------------------------------
@@ -414,12 +584,16 @@ __device__ CellSort cell_sort(double *xs, double *vals, int N, const int kmin[3]
 // of the grid field f (real R, [3][nz][ny][nx], accumulated): per occupied
 // cell a 4x3x3 register block, added once to the FP64 LDS tile whose non-zero
 // points are then added to f with device atomics; without a tile, every node
-// adds its 27 weights to f directly.
+// adds its 27 weights to f directly.  The atomics are not waited for (the
+// barriers here order LDS only).  before_last_flush() is called by every
+// thread once the last lattice's tile is complete (tile path only), so that a
+// caller can issue loads that overlap the last flush.
 // ---------------------------------------------------------------------------
-template <typename R, int NT>
+template <typename R, int NT, typename BeforeLastFlush>
 __device__ void spread_to_grid(const double *xs, const double *vals, int N, const CellSort &cs,
                                const uint16_t *occ_start, const uint16_t *occ_cnt, double *ftile,
-                               R *f, int64_t field, double inv_h, double inv_h3, bool &bad) {
+                               R *f, int64_t field, double inv_h, double inv_h3, bool &bad,
+                               BeforeLastFlush before_last_flush) {
     const int tid = threadIdx.x;
     const TileGeom &tg = cs.tg;
 #pragma unroll
@@ -427,7 +601,7 @@ __device__ void spread_to_grid(const double *xs, const double *vals, int N, cons
         R *fd = f + d * field;
         if (cs.use_tile) {
             for (int t = tid; t < tg.T; t += NT) ftile[t] = 0.0;
-            __syncthreads();
+            lds_barrier();
             for (int o = tid; o < cs.n_occ; o += NT) {
                 const int p = occ_start[o], q = p + occ_cnt[o];
                 const int kcell[3] = {cell_of(xs[3 * p], inv_h), cell_of(xs[3 * p + 1], inv_h),
@@ -442,12 +616,14 @@ __device__ void spread_to_grid(const double *xs, const double *vals, int N, cons
                     spread_cell<R, 2>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.T, inv_h,
                                       inv_h3, ftile, bad);
             }
-            __syncthreads();
-            for (int t = tid; t < tg.T; t += NT) {
-                const double v = ftile[t];
-                if (v != 0.0) unsafeAtomicAdd(fd + tg.grid_index(t), (R)v);
+            lds_barrier();
+            if (d == 2) before_last_flush();
+            // the grid atomics stay in flight across the following barriers
+            for (TileCursor c = TileCursor::first(tg); c.t < tg.T; c.template next<NT>(tg)) {
+                const double v = ftile[c.t];
+                if (v != 0.0) unsafeAtomicAdd(fd + c.grid_index(tg), (R)v);
             }
-            __syncthreads();
+            lds_barrier();
         } else {
             for (int p = tid; p < N; p += NT) {
                 R wx[3], wy[3], wz[3];
