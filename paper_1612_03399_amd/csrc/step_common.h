@@ -15,6 +15,7 @@ namespace {
 
 constexpr int K = kStepNodesPerThread;
 constexpr int kCountBins = 32;     // occupied cells are ordered by node count (capped)
+constexpr int kCellChunk = 8;      // nodes of a cell spread by one thread, at most
 constexpr int FK = kStepFacesPerThread;
 
 
@@ -448,8 +449,9 @@ __device__ __forceinline__ void load_positions(double *xs, const double *X, bool
 // Counting sort of the first N nodes by Eulerian cell (section 5's per-marker
 // cell index): xs and vals ([N][3] each) are permuted in place into cell
 // order, pos[s] receives the new index of node tid + s NT, and the occupied
-// cells are listed (first node, count) ordered by decreasing count, so that
-// the threads of a wave spread cells of similar size.  Skipped (use_tile =
+// cells are listed as work items (first node, count) of at most kCellChunk
+// nodes (a crowded cell gives several), ordered by decreasing count, so that
+// the threads of a wave spread items of similar size.  Skipped (use_tile =
 // false, identity order) when the unit's cell box or grid tile does not fit
 // the tile region.
 // ---------------------------------------------------------------------------
@@ -492,16 +494,19 @@ __device__ CellSort cell_sort(double *xs, double *vals, int N, const int kmin[3]
         }
         __syncthreads();
         int *occ_idx = hist + C;
-        for (int c = tid; c < C; c += NT) occ_idx[c] = hist[c] > 0 ? 1 : 0;
+        // a cell's nodes form ceil(n / kCellChunk) work items of at most
+        // kCellChunk consecutive nodes (each item at least one node, so at most
+        // N items)
+        for (int c = tid; c < C; c += NT) occ_idx[c] = (hist[c] + kCellChunk - 1) / kCellChunk;
         __syncthreads();
         n_occ = uniform(block_exclusive_scan<NT>(occ_idx, C, ired));
         block_exclusive_scan<NT>(hist, C, ired);
         for (int c = tid; c < C; c += NT) {
             const int start = hist[c];
             const int next = c + 1 < C ? hist[c + 1] : N;
-            if (next > start) {
-                occ_start[occ_idx[c]] = (uint16_t)start;
-                occ_cnt[occ_idx[c]] = (uint16_t)(next - start);
+            for (int p = start, o = occ_idx[c]; p < next; p += kCellChunk, ++o) {
+                occ_start[o] = (uint16_t)p;
+                occ_cnt[o] = (uint16_t)min(kCellChunk, next - p);
             }
         }
         if (tid == 0) *n_occ_sh = n_occ;

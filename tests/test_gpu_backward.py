@@ -28,6 +28,9 @@ CASES = {
     "drop_L3_64": lambda: W.config0(),
     "four_L2_32": lambda: W.small_suspension(4, 2, 32),
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
+    # level-4 drops of radius 1.9 h: ~55 nodes per occupied cell, so a
+    # cell's nodes are spread by several work items
+    "crowded_L4_32": lambda: W.small_suspension(2, 4, 32, r=0.06),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
                                          cells_per_unit=64),
     # a shell split into patches by the fused reverse step

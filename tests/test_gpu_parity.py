@@ -36,6 +36,9 @@ CASES = {
     # than a workgroup's lanes, every fused-kernel loop takes several turns
     "four_L4_128": lambda: W.small_suspension(4, 4, 128, r=0.04),
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
+    # level-4 drops of radius 1.9 h: ~55 nodes per occupied cell, so a
+    # cell's nodes are spread by several work items
+    "crowded_L4_32": lambda: W.small_suspension(2, 4, 32, r=0.06),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
                                          cells_per_unit=64),
     # a 16 002-node shell: the fused step splits it into patches with halos
