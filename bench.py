@@ -181,9 +181,17 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
                     dtype=torch.float32) - 0.5) * 0.2
     f = torch.zeros_like(u)
     k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
-    plan = N.Plan(wl, wl.grid, "f32")
-    N.ip_plan_bind_reference(plan, N.ip_reference_from(plan, torch.as_tensor(wl.Xref).to(dev)))
     X = torch.as_tensor(wl.X).to(dev)
+    Xref = torch.as_tensor(wl.Xref).to(dev)
+    from paper_1612_03399_amd import autotune as AT
+    opts, tuned = AT.autotune(wl, wl.grid, "f32", X, None, k, u, wl.dt,
+                              candidates=AT.UNEVEN_CANDIDATES, Xref=Xref)
+    for r in tuned:
+        log(f"  uneven options {r['options']}: {r['ms']:.3f} ms ({r['units']} units, "
+            f"{r['threads']} threads, tile {r['tile_bytes']} B)")
+    plan = N.Plan(wl, wl.grid, "f32", opts)
+    ref = N.ip_reference_from(plan, Xref)
+    N.ip_plan_bind_reference(plan, ref)
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps):
@@ -213,7 +221,8 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags} in the uneven leg")
-    out = {"uneven_workload": wl.name, "uneven_nodes": wl.n_nodes,
+    out = {"uneven_workload": wl.name, "uneven_nodes": wl.n_nodes, "uneven_options": opts,
+           "uneven_autotune": [{"options": r["options"], "ms": r["ms"]} for r in tuned],
            "uneven_units": plan.n_units, "uneven_patched_bodies": plan.patched_bodies,
            "uneven_batched_ms": batched, "uneven_graph_ms": graph,
            "uneven_node_steps_per_s": wl.n_nodes / (graph * 1e-3)}
@@ -222,7 +231,7 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
     ids = np.sort(np.random.default_rng(7).choice(wl.n_bodies, sample, replace=False))
     sub = W.subset(wl, ids)
     ks = N.Constants.from_arrays(sub.ks, sub.kb, sub.kA, sub.kV, sub.mass, dev)
-    bplan = N.Plan(sub, sub.grid, "f32")
+    bplan = N.Plan(sub, sub.grid, "f32", opts)
     N.ip_plan_bind_reference(bplan, N.ip_reference_from(bplan, torch.as_tensor(sub.Xref).to(dev)))
     Xs = torch.as_tensor(sub.X).to(dev)
     sample_batched = timed(lambda: N.ip_step(bplan, Xs, None, ks, u, f, wl.dt, stream=stream), steps)

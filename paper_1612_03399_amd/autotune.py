@@ -18,14 +18,27 @@ from . import native as N
 
 #: Candidate launch shapes: 768 threads with whole bodies up to 3072 nodes,
 #: the same with a capped tile, 384 threads (units up to 1536 nodes, two
-#: workgroups per compute unit when their LDS fits), and 384 threads with
-#: small patches and a capped tile (more, smaller units sharing compute units).
+#: workgroups per compute unit when their LDS fits), 384 threads with small
+#: patches and a capped tile (more, smaller units sharing compute units), and
+#: bodies above 768 or 1536 nodes cut into patches of 256 or 512 owned nodes
+#: (bodies that span many cells get patches whose grid tiles fit LDS).
 CANDIDATES = (
     {},
     {"threads": 768, "tile_bytes": 32768},
     {"threads": 384},
     {"threads": 384, "unit_nodes": 768, "patch_owned": 512, "tile_bytes": 16384},
     {"threads": 384, "unit_nodes": 640, "patch_owned": 384, "tile_bytes": 12288},
+    {"unit_nodes": 768, "patch_owned": 256},
+    {"unit_nodes": 1536, "patch_owned": 512},
+)
+
+#: A shorter list for large batches of uneven bodies, where building each
+#: plan costs seconds: the default, one workgroup per compute unit with the
+#: largest tiles, and small patches two per compute unit.
+UNEVEN_CANDIDATES = (
+    {},
+    {"threads": 384},
+    {"unit_nodes": 768, "patch_owned": 256},
 )
 
 
@@ -50,15 +63,20 @@ def time_plan(plan, X, ref, k, u, dt, steps=5, warmup=2, f=None):
     return e0.elapsed_time(e1) / steps
 
 
-def autotune(mesh, grid, precision, X, ref, k, u, dt, candidates=CANDIDATES, steps=5, warmup=2):
+def autotune(mesh, grid, precision, X, ref, k, u, dt, candidates=CANDIDATES, steps=5, warmup=2,
+             Xref=None):
     """Returns (best options dict, list of per-candidate results).  `ref` is a
-    native.Reference of the mesh (caller's element order); X, u on the device."""
+    native.Reference of the mesh (caller's element order), or None with the
+    reference positions `Xref` given (the reference is then computed once,
+    with the first candidate's plan); X, u on the device."""
     results = []
     seen = set()
     f = torch.zeros_like(u)
     for opt in candidates:
         plan = N.Plan(mesh, grid, precision, opt)
         try:
+            if ref is None:
+                ref = N.ip_reference_from(plan, Xref)
             shape = (plan.fused, plan.n_units, plan.step_threads, plan.tile_bytes,
                      plan.largest_unit)
             if shape in seen:          # resolves to a launch shape already timed

@@ -177,6 +177,8 @@ LAUNCH_SHAPES = {
     "t384_small_units": {"threads": 384, "unit_nodes": 640, "patch_owned": 384,
                          "tile_bytes": 12288},
     "t768_tile8k": {"tile_bytes": 8192},
+    "patch256": {"unit_nodes": 768, "patch_owned": 256},
+    "patch512": {"unit_nodes": 1536, "patch_owned": 512},
 }
 
 
@@ -190,6 +192,21 @@ def test_step_parity_launch_shapes(case, shape):
     # 384-thread workgroups and larger ones on 768
     assert plan.fused and plan.step_threads == opts.get("threads", plan.step_threads)
     assert plan.step_threads in (384, 768)
+
+
+def test_autotune_choice_computes_the_step():
+    """The autotuner (reference computed from the reference positions with its
+    first plan) returns one of its candidates, times every distinct launch
+    shape, and the shape it picks computes the step to parity."""
+    from paper_1612_03399_amd import autotune as AT
+    say("autotune four_L4_128")
+    wl = CASES["four_L4_128"]()
+    u = dev(wl.velocity())
+    opts, results = AT.autotune(wl, wl.grid, "f64", dev(wl.X), None, constants(wl), u, wl.dt,
+                                steps=2, warmup=1, Xref=dev(wl.Xref))
+    assert opts in [dict(c) for c in AT.CANDIDATES]
+    assert len(results) >= 2 and all(r["ms"] > 0 for r in results)
+    check_step("four_L4_128", "f64", True, opts)
 
 
 def test_forces_deterministic():
