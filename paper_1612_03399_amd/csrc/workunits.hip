@@ -13,6 +13,7 @@
 // into the same node accumulator).
 #include <algorithm>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "ipibm_internal.h"
@@ -20,41 +21,62 @@
 namespace {
 
 // Greedy first fit of the elements into groups of 64 with pairwise distinct
-// nodes (local ids, -1 = none).
+// nodes (local ids, -1 = none): element e goes to the lowest group that is not
+// full and holds none of its nodes.  The candidate groups are examined 64 at a
+// time as a bit mask (the window starts at the lowest group that is not full),
+// so one pass over the element's nodes' group lists finds the group.
 void conflict_free_order(int count, int width, const int32_t *elem, int n_nodes,
                          std::vector<std::vector<int32_t>> &node_groups,
-                         std::vector<int32_t> &order) {
+                         std::vector<int32_t> &group_of, std::vector<int32_t> &order) {
     constexpr int G = 64;
     if ((int)node_groups.size() < n_nodes) node_groups.resize(n_nodes);
     for (int v = 0; v < n_nodes; ++v) node_groups[v].clear();
-    std::vector<std::vector<int32_t>> groups;
-    size_t g0 = 0;
+    std::vector<int32_t> size;          // elements per group
+    group_of.resize(count);
+    size_t g0 = 0;                      // lowest group that is not full
+    uint64_t fullw = 0;                 // bit i: group g0 + i is full
     for (int e = 0; e < count; ++e) {
-        size_t g = g0;
-        for (;; ++g) {
-            if (g == groups.size()) groups.emplace_back();
-            if ((int)groups[g].size() >= G) continue;
-            bool clash = false;
-            for (int r = 0; r < width && !clash; ++r) {
+        size_t base = g0;
+        uint64_t full = fullw;
+        size_t g;
+        for (;;) {
+            uint64_t busy = full;
+            for (int r = 0; r < width; ++r) {
                 const int v = elem[e * width + r];
                 if (v < 0) continue;
-                for (int32_t gg : node_groups[v])
-                    if ((size_t)gg == g) {
-                        clash = true;
-                        break;
-                    }
+                for (int32_t gg : node_groups[v]) {
+                    const size_t d = (size_t)gg - base;   // wraps for gg < base
+                    if (d < 64) busy |= 1ull << d;
+                }
             }
-            if (!clash) break;
+            if (busy != ~0ull) {
+                g = base + (size_t)__builtin_ctzll(~busy);
+                break;
+            }
+            base += 64;                 // every group of this window is taken
+            full = 0;
+            for (int i = 0; i < 64 && base + i < size.size(); ++i)
+                if (size[base + i] >= G) full |= 1ull << i;
         }
-        groups[g].push_back(e);
+        if (g >= size.size()) size.resize(g + 1, 0);
+        group_of[e] = (int32_t)g;
+        ++size[g];
         for (int r = 0; r < width; ++r) {
             const int v = elem[e * width + r];
             if (v >= 0) node_groups[v].push_back((int32_t)g);
         }
-        while (g0 < groups.size() && (int)groups[g0].size() >= G) ++g0;
+        if (size[g] >= G && g - g0 < 64) fullw |= 1ull << (g - g0);
+        while (g0 < size.size() && size[g0] >= G) {
+            ++g0;
+            fullw >>= 1;
+            if (g0 + 63 < size.size() && size[g0 + 63] >= G) fullw |= 1ull << 63;
+        }
     }
-    order.clear();
-    for (auto &g : groups) order.insert(order.end(), g.begin(), g.end());
+    // elements by group, in element order within a group
+    std::vector<int32_t> start(size.size() + 1, 0);
+    for (size_t i = 0; i < size.size(); ++i) start[i + 1] = start[i] + size[i];
+    order.resize(count);
+    for (int e = 0; e < count; ++e) order[start[group_of[e]]++] = e;
 }
 
 struct Builder {
@@ -62,7 +84,7 @@ struct Builder {
     WorkUnits &out;
     int whole_max, nmax_unit, fmax_unit, patch_owned;
     std::vector<std::vector<int32_t>> node_groups;
-    std::vector<int32_t> loc, order;
+    std::vector<int32_t> loc, order, group_of;
 
     // Append one unit: `nodes` = global ids (owned first) or empty for a whole
     // body; `edges`, `faces` = global element ids; `local` maps global node
@@ -84,7 +106,7 @@ struct Builder {
                 const int32_t v = m->edges4[4 * (int64_t)edges[i] + r];
                 loc[4 * i + r] = v < 0 ? -1 : local[v - n0];
             }
-        conflict_free_order((int)edges.size(), 4, loc.data(), n_unit, node_groups, order);
+        conflict_free_order((int)edges.size(), 4, loc.data(), n_unit, node_groups, group_of, order);
         u.edge_begin = (int64_t)out.edge_perm.size();
         for (int32_t i : order) {
             out.edge_perm.push_back(edges[i]);
@@ -96,7 +118,7 @@ struct Builder {
         loc.resize(3 * faces.size());
         for (size_t i = 0; i < faces.size(); ++i)
             for (int r = 0; r < 3; ++r) loc[3 * i + r] = local[m->faces[3 * (int64_t)faces[i] + r] - n0];
-        conflict_free_order((int)faces.size(), 3, loc.data(), n_unit, node_groups, order);
+        conflict_free_order((int)faces.size(), 3, loc.data(), n_unit, node_groups, group_of, order);
         u.face_begin = (int64_t)out.face_perm.size();
         for (int32_t i : order) {
             out.face_perm.push_back(faces[i]);
@@ -250,9 +272,60 @@ struct Builder {
 bool build_work_units(const ip_mesh *m, int whole_max, int nmax_unit, int fmax_unit,
                       int patch_owned, WorkUnits &out) {
     out = WorkUnits{};
-    Builder bld{m, out, whole_max, nmax_unit, fmax_unit, patch_owned, {}, {}, {}};
-    for (int b = 0; b < m->n_bodies; ++b)
-        if (!bld.build_body(b)) return false;
+    const int B = m->n_bodies;
+    // contiguous runs of bodies of about equal size (nodes + elements), one
+    // per host thread; concatenated in body order, the result does not depend
+    // on the thread count
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::max(1, std::min({(int)std::min(hw, 16u), B / 16, 16}));
+    std::vector<int64_t> cost(B + 1, 0);
+    for (int b = 0; b < B; ++b)
+        cost[b + 1] = cost[b] + (m->node_off[b + 1] - m->node_off[b]) +
+                      (m->edge_off[b + 1] - m->edge_off[b]) + (m->face_off[b + 1] - m->face_off[b]);
+    std::vector<int> cut(T + 1, B);
+    cut[0] = 0;
+    for (int t = 1; t < T; ++t)
+        cut[t] = (int)(std::lower_bound(cost.begin(), cost.end(), cost[B] * t / T) - cost.begin());
+    for (int t = 1; t <= T; ++t) cut[t] = std::max(cut[t], cut[t - 1]);
+    std::vector<WorkUnits> parts(T);
+    std::vector<char> ok(T, 1);
+    const auto run = [&](int t) {
+        try {
+            Builder bld{m, parts[t], whole_max, nmax_unit, fmax_unit, patch_owned, {}, {}, {}, {}};
+            for (int b = cut[t]; b < cut[t + 1]; ++b)
+                if (!bld.build_body(b)) {
+                    ok[t] = 0;
+                    return;
+                }
+        } catch (...) {
+            ok[t] = 0;
+        }
+    };
+    std::vector<std::thread> threads;
+    for (int t = 1; t < T; ++t) threads.emplace_back(run, t);
+    run(0);
+    for (auto &th : threads) th.join();
+    for (int t = 0; t < T; ++t)
+        if (!ok[t]) return false;
+    for (auto &p : parts) {
+        const int64_t dn = (int64_t)out.nodes.size(), de = (int64_t)out.edge_perm.size(),
+                      df = (int64_t)out.face_perm.size();
+        for (auto u : p.units) {
+            u.node_begin += dn;
+            u.node_end += dn;
+            u.edge_begin += de;
+            u.edge_end += de;
+            u.face_begin += df;
+            u.face_end += df;
+            out.units.push_back(u);
+        }
+        out.nodes.insert(out.nodes.end(), p.nodes.begin(), p.nodes.end());
+        out.edge_perm.insert(out.edge_perm.end(), p.edge_perm.begin(), p.edge_perm.end());
+        out.edge_lid.insert(out.edge_lid.end(), p.edge_lid.begin(), p.edge_lid.end());
+        out.face_perm.insert(out.face_perm.end(), p.face_perm.begin(), p.face_perm.end());
+        out.face_lid.insert(out.face_lid.end(), p.face_lid.begin(), p.face_lid.end());
+        p = WorkUnits{};
+    }
     // largest units first (the tail of the launch runs the small ones)
     std::vector<int32_t> idx(out.units.size());
     std::iota(idx.begin(), idx.end(), 0);
@@ -260,6 +333,7 @@ bool build_work_units(const ip_mesh *m, int whole_max, int nmax_unit, int fmax_u
         return out.units[x].n_nodes > out.units[y].n_nodes;
     });
     std::vector<WorkUnitHost> sorted;
+    sorted.reserve(idx.size());
     for (int i : idx) sorted.push_back(out.units[i]);
     out.units.swap(sorted);
     return true;
