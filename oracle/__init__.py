@@ -18,7 +18,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle_core.inc")]
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle_core.inc"),
+        os.path.join(_HERE, "oracle_mls.inc")]
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -59,6 +60,17 @@ def lib():
         L.orc_taylor.argtypes = [C.c_int, i64, d, d, d]
         L.orc_taylor_loss_grad.restype = C.c_double
         L.orc_taylor_loss_grad.argtypes = [C.c_int, i64, d, d, d]
+        L.orc_centroids.argtypes = [C.c_int64, i32, d, d, d]
+        L.orc_mls_shape.restype = C.c_int
+        L.orc_mls_shape.argtypes = [C.c_int64, d, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                    C.c_double, i64, d]
+        L.orc_interp_mls.restype = C.c_int
+        L.orc_interp_mls.argtypes = [C.c_int64, d, C.c_int, C.c_int, C.c_int, C.c_double,
+                                     C.c_double, d, d]
+        L.orc_spread_mls.restype = C.c_int
+        L.orc_spread_mls.argtypes = [C.c_int64, d, d, d, C.c_int, C.c_int, C.c_int, C.c_double,
+                                     C.c_double, d]
+        L.orc_centroid_to_nodes.argtypes = [C.c_int64, C.c_int64, i32, d, d]
         _lib = L
     return _lib
 
@@ -293,3 +305,68 @@ def rollout_grad(m, X0, ref: Reference, u, dt, steps, Dstar, k=None):
         spread(Xn, P, m.grid, gu_tmp := np.zeros_like(gu))
         gu += dt * h ** 3 * gu_tmp
     return dict(loss=loss, gX0=lam, gk=gk, gu=gu, X_final=Xs[-1])
+
+
+# ---- MLS transfer at the triangle centroids (Section 2.2; oracle_mls.inc) ----
+
+def centroids(m, X):
+    """Face centroids C[F][3] (the Lagrangian markers) and face areas A[F]."""
+    fa = np.ascontiguousarray(m.faces, np.int32)
+    X = _f64(X)
+    Cc = np.zeros((len(fa), 3))
+    Af = np.zeros(len(fa))
+    lib().orc_centroids(len(fa), _p(fa, C.c_int32), _p(X, C.c_double), _p(Cc, C.c_double),
+                        _p(Af, C.c_double))
+    return Cc, Af
+
+
+def mls_shape(P, grid, d, alpha):
+    """Support indices idx[M][27] (flat in one lattice) and MLS shape
+    functions phi[M][27] of positions P on lattice d."""
+    P = _f64(P)
+    M = len(P)
+    idx = np.zeros((M, 27), np.int64)
+    phi = np.zeros((M, 27))
+    nx, ny, nz, h = _grid(grid)
+    bad = lib().orc_mls_shape(M, _p(P, C.c_double), int(d), nx, ny, nz, h, float(alpha),
+                              _p(idx, C.c_int64), _p(phi, C.c_double))
+    assert bad == 0, f"{bad} singular moment matrices"
+    return idx, phi
+
+
+def interp_mls(P, grid, u, alpha):
+    """U[M][3] at positions P, component d from lattice d of u."""
+    P = _f64(P)
+    u = _f64(u)
+    U = np.zeros((len(P), 3))
+    nx, ny, nz, h = _grid(grid)
+    bad = lib().orc_interp_mls(len(P), _p(P, C.c_double), nx, ny, nz, h, float(alpha),
+                               _p(u, C.c_double), _p(U, C.c_double))
+    assert bad == 0, f"{bad} singular moment matrices"
+    return U
+
+
+def spread_mls(P, Am, Fm, grid, alpha, f=None):
+    """f += MLS spreading of the marker force densities Fm[M][3] (marker
+    areas Am[M]) with the force-conserving factor c_l."""
+    P = _f64(P)
+    nx, ny, nz, h = _grid(grid)
+    if f is None:
+        f = np.zeros((3, nz, ny, nx))
+    assert f.dtype == np.float64 and f.flags.c_contiguous
+    bad = lib().orc_spread_mls(len(P), _p(P, C.c_double), _p(_f64(Am), C.c_double),
+                               _p(_f64(Fm), C.c_double), nx, ny, nz, h, float(alpha),
+                               _p(f, C.c_double))
+    assert bad == 0, f"{bad} singular moment matrices"
+    return f
+
+
+def centroid_to_nodes(m, Fc):
+    """Vertex forces: each vertex takes one third of the centroid force of
+    every face it belongs to."""
+    fa = np.ascontiguousarray(m.faces, np.int32)
+    N = int(np.asarray(m.node_off)[-1])
+    Fn = np.zeros((N, 3))
+    lib().orc_centroid_to_nodes(N, len(fa), _p(fa, C.c_int32), _p(_f64(Fc), C.c_double),
+                                _p(Fn, C.c_double))
+    return Fn

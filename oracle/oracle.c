@@ -291,3 +291,6 @@ double orc_taylor_loss_grad(int B, const int64_t *node_off, const double *X,
     }
     return loss;
 }
+
+/* ---------------- MLS transfer at the triangle centroids ---------------- */
+#include "oracle_mls.inc"

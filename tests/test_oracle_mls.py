@@ -1,0 +1,200 @@
+"""Pins of the oracle's MLS transfer at the triangle centroids (Section 2.2:
+the MLS equations, the exponential weight on a 3x3x3 support of threshold
+1.5 h, the force-conserving factor c_l; Section 2.3: one third of a centroid
+force to each vertex).  Each pin checks the oracle against something other
+than its own formulas: exact reproduction of linear fields (a property of
+MLS with a linear basis), a closed form at a lattice point, numpy's
+least-squares solver, conservation laws and the adjoint identity."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1612_03399_amd import workload as W
+
+OFF = np.array([[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
+
+
+def grid(n=16, h=1.0 / 16):
+    return W.Grid(n, n, n, h)
+
+
+def markers(rng, g, m=40):
+    """Positions well inside the box (no periodic wrap within the support)."""
+    L = g.nx * g.h
+    return rng.uniform(0.3 * L, 0.7 * L, size=(m, 3))
+
+
+def lattice_points(g, d):
+    """Physical coordinates of every point of lattice d, [nz][ny][nx][3]."""
+    k, j, i = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    return np.stack([(i + OFF[d, 0]) * g.h, (j + OFF[d, 1]) * g.h, (k + OFF[d, 2]) * g.h], axis=-1)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 1.0])
+def test_linear_fields_reproduced(alpha):
+    """MLS with the basis [1, x, y, z] reproduces any linear field exactly."""
+    rng = np.random.default_rng(1)
+    g = grid()
+    P = markers(rng, g)
+    a = rng.normal(size=3)
+    b = rng.normal(size=(3, 3))
+    u = np.stack([a[d] + lattice_points(g, d) @ b[d] for d in range(3)])
+    U = O.interp_mls(P, g, u, alpha)
+    want = a[None, :] + P @ b.T
+    assert np.abs(U - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_marker_on_a_lattice_point():
+    """At a lattice point the support is symmetric, the linear coefficients
+    vanish and phi_k = W_k / sum W: the centre weighs
+    1 / (1 + 2 exp(-(2/(3 alpha))^2))^3 (neighbours at distance h = r 1.5 h
+    with r = 2/3)."""
+    g = grid()
+    alpha = 0.4
+    for d in range(3):
+        p = (np.array([7, 8, 9]) + OFF[d]) * g.h
+        idx, phi = O.mls_shape(p[None, :], g, d, alpha)
+        e = np.exp(-(2.0 / (3.0 * alpha)) ** 2)
+        centre = 1.0 / (1.0 + 2.0 * e) ** 3
+        assert abs(phi[0, 13] - centre) <= 1e-14
+        # the 27 weights are products of (e, 1, e) per axis, normalised
+        w1 = np.array([e, 1.0, e])
+        want = np.einsum("i,j,k->ijk", w1, w1, w1).ravel() / (1 + 2 * e) ** 3
+        assert np.abs(phi[0] - want).max() <= 1e-14
+        # the centre index is the lattice point itself
+        assert idx[0, 13] == (9 * g.ny + 8) * g.nx + 7
+
+
+def support_geometry(p, g, d):
+    """Support offsets (x^k - x)/h of the 27 nearest points, kx fastest."""
+    s = p / g.h - OFF[d]
+    c = np.floor(s + 0.5)
+    out = []
+    for kz in (-1, 0, 1):
+        for ky in (-1, 0, 1):
+            for kx in (-1, 0, 1):
+                out.append(c + np.array([kx, ky, kz]) - s)
+    return np.array(out)
+
+
+def test_unweighted_limit_is_least_squares():
+    """For alpha -> infinity every support point weighs 1 and the MLS value is
+    the ordinary least-squares linear fit over the 27 points (numpy lstsq)."""
+    rng = np.random.default_rng(2)
+    g = grid()
+    P = markers(rng, g, 10)
+    for d in range(3):
+        idx, phi = O.mls_shape(P, g, d, 1e8)
+        for m in range(len(P)):
+            D = support_geometry(P[m], g, d)
+            Amat = np.hstack([np.ones((27, 1)), D])
+            q = rng.normal(size=27)
+            coef = np.linalg.lstsq(Amat, q, rcond=None)[0]
+            assert abs(phi[m] @ q - coef[0]) <= 1e-12 * np.abs(q).max()
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.6])
+def test_weighted_least_squares(alpha):
+    """For finite alpha the value is the weighted least-squares fit with the
+    weights exp(-(r/alpha)^2) per axis, r = |offset| / 1.5 (numpy lstsq on
+    the sqrt(W)-scaled system)."""
+    rng = np.random.default_rng(3)
+    g = grid()
+    P = markers(rng, g, 10)
+    for d in range(3):
+        _, phi = O.mls_shape(P, g, d, alpha)
+        for m in range(len(P)):
+            D = support_geometry(P[m], g, d)
+            w = np.prod(np.exp(-((np.abs(D) / 1.5) / alpha) ** 2), axis=1)
+            Amat = np.hstack([np.ones((27, 1)), D]) * np.sqrt(w)[:, None]
+            q = rng.normal(size=27)
+            coef = np.linalg.lstsq(Amat, q * np.sqrt(w), rcond=None)[0]
+            assert abs(phi[m] @ q - coef[0]) <= 1e-12 * np.abs(q).max()
+
+
+def test_spreading_conserves_force_and_moment():
+    """With c_l the total force sum_k f^k h^3 equals sum_l dV_l F_l, dV_l =
+    A_l h_l, h_l = h on a uniform grid; by linear reproduction the first
+    moment (torque about the origin) is conserved as well."""
+    rng = np.random.default_rng(4)
+    g = grid()
+    P = markers(rng, g)
+    Am = rng.uniform(0.5, 2.0, size=len(P)) * g.h ** 2
+    Fm = rng.normal(size=(len(P), 3))
+    f = O.spread_mls(P, Am, Fm, g, 0.35)
+    h3 = g.h ** 3
+    for d in range(3):
+        tot = f[d].sum() * h3
+        want = (Am * g.h * Fm[:, d]).sum()
+        assert abs(tot - want) <= 1e-12 * np.abs(Am * g.h * Fm[:, d]).sum()
+        X = lattice_points(g, d)
+        mom = np.einsum("zyxa,zyx->a", X, f[d]) * h3
+        want_m = ((Am * g.h * Fm[:, d])[:, None] * P).sum(axis=0)
+        assert np.abs(mom - want_m).max() <= 1e-12 * np.abs(want_m).max()
+
+
+def test_spreading_is_adjoint_of_interpolation():
+    """sum_k f^k u^k h^3 = sum_l c_l h^3 F_l . U_l with c_l h^3 = A_l h."""
+    rng = np.random.default_rng(5)
+    g = grid()
+    P = markers(rng, g)
+    Am = rng.uniform(0.5, 2.0, size=len(P)) * g.h ** 2
+    Fm = rng.normal(size=(len(P), 3))
+    u = rng.normal(size=(3, g.nz, g.ny, g.nx))
+    f = O.spread_mls(P, Am, Fm, g, 0.5)
+    U = O.interp_mls(P, g, u, 0.5)
+    lhs = (f * u).sum() * g.h ** 3
+    rhs = ((Am * g.h)[:, None] * Fm * U).sum()
+    assert abs(lhs - rhs) <= 1e-12 * np.abs((Am * g.h)[:, None] * Fm * U).sum()
+
+
+def test_periodic_wrap_matches_shifted_marker():
+    """A marker near the box edge reads the wrapped lattice: shifting the
+    marker and the field by whole periods changes nothing."""
+    rng = np.random.default_rng(6)
+    g = grid()
+    u = rng.normal(size=(3, g.nz, g.ny, g.nx))
+    p = np.array([[0.01, 0.5, 0.99]])
+    U0 = O.interp_mls(p, g, u, 0.4)
+    U1 = O.interp_mls(p + np.array([[1.0, -1.0, 2.0]]), g, u, 0.4)
+    assert np.abs(U0 - U1).max() <= 1e-12
+
+
+def test_centroids_and_areas():
+    """Closed forms on a right triangle and a regular icosahedron (all faces
+    of area sqrt(3)/4 a^2, centroids at the inradius)."""
+    X = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 3.0, 0.0]])
+
+    class M:
+        faces = np.array([[0, 1, 2]], np.int32)
+        node_off = np.array([0, 3])
+
+    Cc, Af = O.centroids(M, X)
+    assert np.allclose(Cc, [[2.0 / 3.0, 1.0, 0.0]], atol=1e-15) and abs(Af[0] - 3.0) <= 1e-15
+    v, f = W.icosphere(0)
+    M.faces = np.asarray(f, np.int32)
+    M.node_off = np.array([0, len(v)])
+    Cc, Af = O.centroids(M, v)
+    a = np.linalg.norm(v[f[0][0]] - v[f[0][1]])
+    assert np.abs(Af - np.sqrt(3.0) / 4.0 * a * a).max() <= 1e-14
+    r_in = np.linalg.norm(Cc, axis=1)
+    assert np.abs(r_in - r_in[0]).max() <= 1e-14
+
+
+def test_centroid_forces_to_vertices():
+    """Each vertex takes one third of every incident face's force: by hand on
+    two triangles sharing an edge, and total force conserved on a sphere."""
+    class M:
+        faces = np.array([[0, 1, 2], [1, 3, 2]], np.int32)
+        node_off = np.array([0, 4])
+
+    Fc = np.array([[3.0, 0.0, 0.0], [0.0, 6.0, 0.0]])
+    Fn = O.centroid_to_nodes(M, Fc)
+    want = np.array([[1, 0, 0], [1, 2, 0], [1, 2, 0], [0, 2, 0]], float)
+    assert np.array_equal(Fn, want)
+    v, f = W.icosphere(2)
+    M.faces = np.asarray(f, np.int32)
+    M.node_off = np.array([0, len(v)])
+    Fc = np.random.default_rng(7).normal(size=(len(f), 3))
+    Fn = O.centroid_to_nodes(M, Fc)
+    assert np.abs(Fn.sum(0) - Fc.sum(0)).max() <= 1e-12
