@@ -212,6 +212,38 @@ ip_status ibm_interp(ip_plan *plan, const double *X, const void *u, void *U, voi
  * Uses device atomics on f: the summation order is not fixed. */
 ip_status ibm_spread(ip_plan *plan, const double *X, const void *F, void *f, void *stream);
 
+/* Moving-least-squares transfer at the triangle centroids (Section 2.2: the
+ * centroids are the Lagrangian markers; the MLS equations with the linear
+ * basis [1, x, y, z]; the exponential weight on the 3x3x3 support of
+ * threshold 1.5 h).  Marker l is the centroid of face l, for every face of
+ * the plan's mesh.  Readings of the paper: the weight is a product over the
+ * axes, W_k = prod_a w(|x_a - x^k_a| / (1.5 h)), w(r) = exp(-(r/alpha)^2)
+ * for r <= 1 (the paper's r_i is the support size in direction i); the
+ * moment matrix is A = sum_k W_k p(x^k) p(x^k)^T.  alpha > 0 is the shape
+ * parameter, which the paper does not fix.
+ * ibm_interp_mls: U[F][3] (real, overwritten), component d interpolated from
+ * lattice d of u (real[3][nz][ny][nx]): U_{l,d} = sum_k phi_k u_d[k], with
+ * phi^T = p(x)^T A^{-1} B.  Requires a grid; alpha must be positive and
+ * finite.  A non-finite shape function sets IP_STATUS_NONFINITE. */
+ip_status ibm_interp_mls(ip_plan *plan, const double *X, const void *u, double alpha, void *U,
+                         void *stream);
+
+/* Spreading of the marker force densities Fm[F][3] (real) with the same
+ * shape functions and the force-conserving factor of Section 2.2:
+ * f_d[k] += c_l phi_k Fm_{l,d}, c_l = dV_l / sum_k phi_k dV^k, dV_l = A_l h_l,
+ * h_l = (1/3) sum_k phi_k (dx + dy + dz), dV^k = h^3, A_l the face area, so
+ * that sum_k f_d[k] h^3 = sum_l dV_l Fm_{l,d}.  f: real[3][nz][ny][nx],
+ * ACCUMULATED (caller zeroes it), device atomics (summation order not
+ * fixed).  Requires a grid; alpha positive and finite. */
+ip_status ibm_spread_mls(ip_plan *plan, const double *X, const void *Fm, double alpha, void *f,
+                         void *stream);
+
+/* Centroid forces to the vertices (Section 2.3): Fn[n] = (1/3) sum of Fc[f]
+ * over the faces f of vertex n.  Fc: real[F][3]; Fn: real[N][3]
+ * (overwritten).  A gather over the plan's per-node lists: no atomics,
+ * bitwise reproducible. */
+ip_status ip_centroid_to_nodes(ip_plan *plan, const void *Fc, void *Fn, void *stream);
+
 /* One explicit step (Section 2.3 Newton update, loosely coupled; the external
  * load is the immersed-boundary reaction m (U - Xdot)/dt of Section 2.2's
  * direct forcing, so that Xdot = U + (dt/m) F):

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libipibm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "workunits.hip", "k_forces.hip", "k_transfer.hip", "k_step.hip",
+SOURCES = ["api.hip", "workunits.hip", "k_forces.hip", "k_transfer.hip", "k_mls.hip", "k_step.hip",
            "k_backward.hip"]
 
 HIPCC_FLAGS = [

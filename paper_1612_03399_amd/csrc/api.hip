@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <cmath>
+
 #include "ipibm_internal.h"
 
 namespace {
@@ -436,6 +438,36 @@ ip_status ibm_spread(ip_plan *plan, const double *X, const void *F, void *f, voi
     if (!aligned(X, 8) || !aligned(F, plan->real_size()) || !aligned(f, plan->real_size()))
         return arg_error("misaligned array");
     return launch_spread(plan, X, F, f, (hipStream_t)stream);
+}
+
+ip_status ibm_interp_mls(ip_plan *plan, const double *X, const void *u, double alpha, void *U,
+                         void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return arg_error("alpha must be positive and finite");
+    if (plan->F > 0 && (!X || !u || !U)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(u, plan->real_size()) || !aligned(U, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_interp_mls(plan, X, u, alpha, U, (hipStream_t)stream);
+}
+
+ip_status ibm_spread_mls(ip_plan *plan, const double *X, const void *Fm, double alpha, void *f,
+                         void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return arg_error("alpha must be positive and finite");
+    if (plan->F > 0 && (!X || !Fm || !f)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(Fm, plan->real_size()) || !aligned(f, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_spread_mls(plan, X, Fm, alpha, f, (hipStream_t)stream);
+}
+
+ip_status ip_centroid_to_nodes(ip_plan *plan, const void *Fc, void *Fn, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (plan->N > 0 && (!Fn || (plan->F > 0 && !Fc))) return arg_error("NULL array");
+    if (!aligned(Fc, plan->real_size()) || !aligned(Fn, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_centroid_to_nodes(plan, Fc, Fn, (hipStream_t)stream);
 }
 
 ip_status ip_step(ip_plan *plan, double *X, const ip_reference *ref, const ip_constants *k,

@@ -164,6 +164,12 @@ ip_status launch_forces(ip_plan *p, const double *X, const ip_reference *ref,
                         hipStream_t s);
 ip_status launch_interp(ip_plan *p, const double *X, const void *u, void *U, hipStream_t s);
 ip_status launch_spread(ip_plan *p, const double *X, const void *F, void *f, hipStream_t s);
+// MLS transfer at the triangle centroids (k_mls.hip)
+ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double alpha, void *U,
+                            hipStream_t s);
+ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double alpha, void *f,
+                            hipStream_t s);
+ip_status launch_centroid_to_nodes(ip_plan *p, const void *Fc, void *Fn, hipStream_t s);
 ip_status launch_update(ip_plan *p, double *X, const void *U, const void *F,
                         const ip_constants *k, double dt, hipStream_t s);
 

@@ -81,6 +81,9 @@ def _load():
         "ip_step_vjp": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, d, vp, vp,
                         vp, vp, vp],
         "ip_taylor": [vp, vp, vp, vp, vp, vp, vp],
+        "ibm_interp_mls": [vp, vp, vp, d, vp, vp],
+        "ibm_spread_mls": [vp, vp, vp, d, vp, vp],
+        "ip_centroid_to_nodes": [vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +253,30 @@ def ibm_interp(plan: Plan, X, u, U=None, stream=None):
 def ibm_spread(plan: Plan, X, F, f, stream=None):
     _check(LIB.ibm_spread(plan.handle, _ptr(X), _ptr(F), _ptr(f), _stream(stream)))
     return f
+
+
+def ibm_interp_mls(plan: Plan, X, u, alpha, U=None, stream=None):
+    """MLS interpolation to the face centroids: U[F][3] (real)."""
+    if U is None:
+        U = torch.empty(plan.F, 3, dtype=plan.dtype, device=X.device)
+    _check(LIB.ibm_interp_mls(plan.handle, _ptr(X), _ptr(u), float(alpha), _ptr(U),
+                              _stream(stream)))
+    return U
+
+
+def ibm_spread_mls(plan: Plan, X, Fm, alpha, f, stream=None):
+    """f += MLS spreading of the centroid force densities Fm[F][3]."""
+    _check(LIB.ibm_spread_mls(plan.handle, _ptr(X), _ptr(Fm), float(alpha), _ptr(f),
+                              _stream(stream)))
+    return f
+
+
+def ip_centroid_to_nodes(plan: Plan, Fc, Fn=None, stream=None):
+    """Vertex forces Fn[N][3]: one third of every incident face's centroid force."""
+    if Fn is None:
+        Fn = torch.empty(plan.N, 3, dtype=plan.dtype, device=Fc.device)
+    _check(LIB.ip_centroid_to_nodes(plan.handle, _ptr(Fc), _ptr(Fn), _stream(stream)))
+    return Fn
 
 
 def ip_step(plan: Plan, X, ref: Reference, k: Constants, u, f, dt, V=None, A=None,
