@@ -260,6 +260,61 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
     return out
 
 
+def mls_leg(N, W, bodies, dev, torch, log, reps=20, alpha=0.4):
+    """MLS transfer at the triangle centroids on the same batch (one marker per
+    face): ibm_interp_mls and ibm_spread_mls timed with HIP events on the launch
+    stream, and their algorithmic bytes: vertex positions read once, face
+    indices, the marker values, and the grid values in the union of the
+    markers' 27-point supports (u read; f read and written)."""
+    wl = W.config1(n_bodies=bodies)
+    log(f"mls leg: {wl.n_faces} markers")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1001)
+    u = (torch.rand((3, wl.grid.nz, wl.grid.ny, wl.grid.nx), generator=g, device=dev,
+                    dtype=torch.float64) - 0.5) * 0.2
+    f = torch.zeros_like(u)
+    Fm = torch.rand((wl.n_faces, 3), generator=g, device=dev, dtype=torch.float64) - 0.5
+    plan = N.Plan(wl, wl.grid, "f64")
+    X = torch.as_tensor(wl.X).to(dev)
+    U = torch.empty(wl.n_faces, 3, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_i = timed(lambda: N.ibm_interp_mls(plan, X, u, alpha, U, stream=stream))
+    t_s = timed(lambda: N.ibm_spread_mls(plan, X, Fm, alpha, f, stream=stream))
+    code, flags = N.ip_plan_status(plan)
+    if code != N.IP_OK:
+        raise SystemExit(f"device status {code} flags {flags} in the mls leg")
+    fa = np.asarray(wl.faces)
+    cen = (wl.X[fa[:, 0]] + wl.X[fa[:, 1]] + wl.X[fa[:, 2]]) / 3.0
+    touched = touched_points(cen, wl.grid)
+    common = wl.n_nodes * 24 + wl.n_faces * 12
+    b_i = common + wl.n_faces * 24 + touched * 8
+    b_s = common + wl.n_faces * 24 + touched * 16
+    out = {"mls_markers": wl.n_faces, "mls_alpha": alpha,
+           "mls_interp_ms": t_i, "mls_spread_ms": t_s,
+           "mls_interp_markers_per_s": wl.n_faces / (t_i * 1e-3),
+           "mls_interp_algorithmic_bytes": b_i, "mls_spread_algorithmic_bytes": b_s,
+           "mls_interp_hbm_frac": b_i / (t_i * 1e-3) / (HBM_PEAK_GBS * 1e9),
+           "mls_spread_hbm_frac": b_s / (t_s * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+    log(f"mls: interp {t_i:.3f} ms ({out['mls_interp_hbm_frac']:.1%} of HBM), "
+        f"spread {t_s:.3f} ms ({out['mls_spread_hbm_frac']:.1%})")
+    del plan, u, f, Fm, U, X
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,8 +327,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other-precision, graph, differentiation and uneven legs")
-    ap.add_argument("--legs", default="other,backward,uneven",
-                    help="extra legs to run: other (other precision + hipGraph), backward, uneven")
+    ap.add_argument("--legs", default="other,backward,uneven,mls",
+                    help="extra legs to run: other (other precision + hipGraph), backward, "
+                         "uneven, mls (MLS transfer at the triangle centroids)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -418,6 +474,8 @@ def main():
         torch.cuda.empty_cache()
     if "backward" in legs and args.precision == "f64":
         extras.update(backward_leg(N, W, args.bodies, dev, torch, log))
+    if "mls" in legs:
+        extras.update(mls_leg(N, W, args.bodies, dev, torch, log))
         torch.cuda.empty_cache()
     if "uneven" in legs:
         extras.update(uneven_leg(N, W, dev, torch, log))

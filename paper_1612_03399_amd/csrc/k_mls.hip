@@ -13,7 +13,19 @@
 // positive definite (all 27 weights are positive inside the support); its
 // Cholesky factor gives z = A^{-1} e_0 and phi_ijk = W_ijk (z0 + z1 dx_i +
 // z2 dy_j + z3 dz_k).  All MLS arithmetic is FP64; the fields are R.
-#include "ipibm_internal.h"
+//
+// Interpolation runs one thread per marker (its gathers of u hit in L2: the
+// faces of a body are consecutive).  Spreading on plans with work units runs
+// one workgroup per unit: the unit's positions go to LDS, each face whose
+// first corner the unit owns adds its 27 weighted values per lattice into an
+// FP64 LDS tile over the cell box of the unit's markers (ds_add_f64), and the
+// tile's non-zero points are added to f once.  A unit whose tile does not fit
+// adds into f directly.  (Measured on 1000 level-4 drops: per-marker global
+// atomics 18.5 ms, the tiled form 0.8 ms; a tiled interpolation was slower
+// than the per-marker one, 0.69 against 0.61 ms.)
+#include <algorithm>
+
+#include "step_common.h"
 
 namespace {
 
@@ -28,6 +40,7 @@ struct MlsShape {
     double dk[3][3];     // per-axis offsets (x^k - x) / h
     double z[4];         // A^{-1} e_0
     int idx[3][3];       // wrapped lattice indices per axis
+    int c[3];            // unwrapped index of the middle support point per axis
 };
 
 __device__ __forceinline__ bool mls_shape(const vec3<double> &x, int d, const MlsGrid &g,
@@ -49,6 +62,7 @@ __device__ __forceinline__ bool mls_shape(const vec3<double> &x, int d, const Ml
             S.w[a][j] = w;
             S.dk[a][j] = dk;
             S.idx[a][j] = wrapi((int)c - 1 + j, n[a]);
+            S.c[a] = (int)c;
             s0[a] += w;
             s1[a] += w * dk;
             s2[a] += w * dk * dk;
@@ -167,6 +181,166 @@ __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
 
+// The centroid's cell (the stencil centre of the lattices staggered by half a
+// cell, as the fused step's tile uses): the supports of all three lattices lie
+// in points cell - 1 .. cell + 2 per axis.
+__device__ __forceinline__ int mls_cell(double x, double inv_h) {
+    double c = floor((x * inv_h - 0.5) + 0.5);      // the expression mls_shape uses
+    if (!(fabs(c) < 1.0e9)) c = 0.0;
+    return (int)c;
+}
+
+// Centroid of the face with unit-local corners q (positions in LDS).
+__device__ __forceinline__ vec3<double> marker_of(const double *xs, const uint16_t *q) {
+    const vec3<double> s = ldx(xs, q[0]) + ldx(xs, q[1]) + ldx(xs, q[2]);
+    return vec3<double>{s.x * (1.0 / 3.0), s.y * (1.0 / 3.0), s.z * (1.0 / 3.0)};
+}
+
+struct MlsUnitArgs {
+    const double *X;
+    const void *Fm;
+    void *f;
+    MlsGrid g;
+    double inv_alpha;
+    uint32_t *status;
+    const int64_t *node_off;
+    const int32_t *wu_body, *wu_owned, *wu_nodes, *frec_perm;
+    const int64_t *wu_noff, *wu_foff;
+    const uint16_t *frec_lid;
+    int nmax, tile_bytes;
+};
+
+// Spreading of the faces owned by one work unit (one workgroup per unit).
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ double red[NT / 64];
+    __shared__ int ired[6 * (NT / 64)];
+    const int tid = threadIdx.x;
+    const int w = blockIdx.x;
+    const int b = a.wu_body[w];
+    const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
+    const bool whole = nl1 == nl0;
+    const int64_t n0 = a.node_off[b];
+    const int NL = whole ? (int)(a.node_off[b + 1] - n0) : (int)(nl1 - nl0);
+    const int N = whole ? NL : a.wu_owned[w];
+    const int32_t *gid = a.wu_nodes + nl0;
+    const int64_t f0 = a.wu_foff[2 * w];
+    const int F = (int)(a.wu_foff[2 * w + 1] - f0);
+    if (NL == 0 || F == 0) return;     // uniform over the block
+    double *xs = (double *)lds;                                  // [nmax][3]
+    double *tile = xs + 3 * a.nmax;                              // tile_bytes
+    const R *Fm = (const R *)a.Fm;
+    R *fld = (R *)a.f;
+    const MlsGrid &g = a.g;
+
+    int lo[3], hi[3];
+    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, g.inv_h, lo, hi);
+    // cell box of the owned markers
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = INT_MAX;
+        hi[c] = INT_MIN;
+    }
+    for (int t = tid; t < F; t += NT) {
+        const uint16_t *q = a.frec_lid + 4 * (f0 + t);
+        if (q[0] >= N) continue;                   // first corner not owned here
+        const vec3<double> p = marker_of(xs, q);
+        const int cc[3] = {mls_cell(p.x, g.inv_h), mls_cell(p.y, g.inv_h), mls_cell(p.z, g.inv_h)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], cc[c]);
+            hi[c] = max(hi[c], cc[c]);
+        }
+    }
+    double none[1] = {0.0};
+    block_box_sums<NT, 1>(lo, hi, none, ired, red);
+    if (lo[0] > hi[0]) return;                     // no owned marker (uniform)
+    // tile points lo - 1 .. hi + 2 per axis
+    const long long Lx = (long long)hi[0] - lo[0] + 4, Ly = (long long)hi[1] - lo[1] + 4,
+                    Lz = (long long)hi[2] - lo[2] + 4;
+    const bool use_tile = Lx <= g.nx && Ly <= g.ny && Lz <= g.nz && Lx * Ly * Lz * 8 <= a.tile_bytes;
+    const int Tx = use_tile ? (int)Lx : 1, Ty = use_tile ? (int)Ly : 1, Tz = use_tile ? (int)Lz : 1;
+    const long long Tl = (long long)Tx * Ty * Tz;
+    TileGeom tg{{lo[0], lo[1], lo[2]}, Tx, Ty, Tz, (int)(use_tile ? Tl : 0), g.nx, g.ny, g.nz,
+                g.plane, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (use_tile) {
+        tg.g0[0] = wrapi(lo[0] - 1, g.nx);
+        tg.g0[1] = wrapi(lo[1] - 1, g.ny);
+        tg.g0[2] = wrapi(lo[2] - 1, g.nz);
+        const int qn = NT / Tx, r = tid / Tx;
+        tg.s[0] = NT % Tx;
+        tg.s[1] = qn % Ty;
+        tg.s[2] = qn / Ty;
+        tg.c0[0] = tid % Tx;
+        tg.c0[1] = r % Ty;
+        tg.c0[2] = r / Ty;
+    }
+    bool bad = false;
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        R *fd = fld + d * g.field;
+        if (use_tile) {
+            for (int t = tid; t < tg.T; t += NT) tile[t] = 0.0;
+            lds_barrier();
+        }
+        for (int t = tid; t < F; t += NT) {
+            const uint16_t *q = a.frec_lid + 4 * (f0 + t);
+            if (q[0] >= N) continue;
+            const vec3<double> xa = ldx(xs, q[0]), xb = ldx(xs, q[1]), xc = ldx(xs, q[2]);
+            const vec3<double> n = cross(xb - xa, xc - xa);
+            const double area = 0.5 * sqrt(dot(n, n));
+            const vec3<double> p = marker_of(xs, q);
+            MlsShape S;
+            bad |= !mls_shape(p, d, g, a.inv_alpha, S);
+            double sphi = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) sphi += mls_phi(S, i, j, k);
+            const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
+            const double cl = area * hl / (sphi * g.h * g.h * g.h);
+            const double Fd = (double)Fm[3 * (int64_t)a.frec_perm[f0 + t] + d] * cl;
+            // support point c - 1 + j is tile point c + j - lo (inside the tile
+            // for every marker the box was taken from; checked all the same)
+            const int ox = S.c[0] - lo[0], oy = S.c[1] - lo[1], oz = S.c[2] - lo[2];
+            const bool in_tile = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Tx &&
+                                 oy + 2 < Ty && oz + 2 < Tz;
+            if (in_tile) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            lds_add(tile + ((oz + k) * Ty + (oy + j)) * Tx + (ox + i),
+                                    mls_phi(S, i, j, k) * Fd);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        R *row = fd + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            unsafeAtomicAdd(row + S.idx[0][i], (R)(mls_phi(S, i, j, k) * Fd));
+                    }
+            }
+        }
+        if (use_tile) {
+            lds_barrier();
+            for (TileCursor c = TileCursor::first(tg); c.t < tg.T; c.template next<NT>(tg)) {
+                const double v = tile[c.t];
+                if (v != 0.0) unsafeAtomicAdd(fd + c.grid_index(tg), (R)v);
+            }
+            lds_barrier();
+        }
+    }
+    if (bad) atomicOr(a.status, IP_STATUS_NONFINITE);
+}
+
 // Fn[n] = (1/3) sum of Fc over the faces of node n (deterministic gather over
 // the node's face-corner slots, slot = 4 E + 3 f + corner).
 template <typename R>
@@ -207,6 +381,33 @@ MlsGrid mls_grid(const ip_plan *p) {
 
 }  // namespace
 
+// Arguments and LDS size of the per-unit kernels: positions [nmax][3] and the
+// largest tile that fits beside them (1 KB kept for the static LDS).
+static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArgs &a,
+                           size_t &lds) {
+    int lds_optin = 0;
+    IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                       p->device));
+    a.X = X;
+    a.g = mls_grid(p);
+    a.inv_alpha = 1.0 / alpha;
+    a.status = p->status;
+    a.node_off = p->node_off;
+    a.wu_body = p->wu_body;
+    a.wu_owned = p->wu_owned;
+    a.wu_nodes = p->wu_nodes;
+    a.frec_perm = p->frec_perm;
+    a.wu_noff = p->wu_noff;
+    a.wu_foff = p->wu_foff;
+    a.frec_lid = p->frec_lid;
+    a.nmax = p->fused_nmax;
+    a.tile_bytes = (int)std::max<long long>((lds_optin - 1024 - 24LL * a.nmax) / 16 * 16, 0);
+    lds = (size_t)24 * a.nmax + (size_t)a.tile_bytes;
+    return IP_OK;
+}
+
+constexpr int kMlsThreads = 512;
+
 ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double alpha, void *U,
                             hipStream_t s) {
     if (p->F == 0) return IP_OK;
@@ -226,6 +427,24 @@ ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double 
                             hipStream_t s) {
     if (p->F == 0) return IP_OK;
     const MlsGrid g = mls_grid(p);
+    if (p->fused_all && p->n_units > 0) {
+        MlsUnitArgs a{};
+        size_t lds = 0;
+        IP_TRY(unit_args(p, X, alpha, a, lds));
+        a.Fm = Fm;
+        a.f = f;
+        const void *fn = p->prec == IP_F64 ? (const void *)k_spread_mls_units<double, kMlsThreads>
+                                           : (const void *)k_spread_mls_units<float, kMlsThreads>;
+        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        if (p->prec == IP_F64)
+            hipLaunchKernelGGL((k_spread_mls_units<double, kMlsThreads>), dim3(p->n_units),
+                               dim3(kMlsThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_spread_mls_units<float, kMlsThreads>), dim3(p->n_units),
+                               dim3(kMlsThreads), lds, s, a);
+        IP_HIP_CHECK(hipGetLastError());
+        return IP_OK;
+    }
     const dim3 grid(nblocks(p->F, 256)), block(256);
     if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_spread_mls<double>, grid, block, 0, s, X, p->faces, p->F,

@@ -20,6 +20,10 @@ CASES = {
     "uneven_small": lambda: W.config2(n_bodies=24, n=64),
     "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
                                          cells_per_unit=64),
+    # a shell split into patches: each face is spread by the unit owning its
+    # first corner
+    "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
+                                           cells_per_unit=96),
 }
 
 
