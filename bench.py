@@ -31,6 +31,10 @@ KERNEL_SOURCES = ["paper_1612_03399_amd/csrc/k_step.hip", "paper_1612_03399_amd/
                   "paper_1612_03399_amd/csrc/ipibm_internal.h",
                   "paper_1612_03399_amd/csrc/workunits.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fused_{workload}_{dtype}.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_k_step_fused_{workload}_{dtype}.json")
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
+# SIMD every 4 cycles (16 lanes per cycle)
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def kernel_source_hash():
@@ -88,6 +92,23 @@ def load_traffic(workload, dtype, launch):
     if t.get("launch") != launch:
         return None, f"taken with launch shape {t.get('launch')}, not {launch}"
     return t["bytes_per_launch"], os.path.relpath(path, ROOT)
+
+
+def load_valu(workload, dtype, launch, ms):
+    """VALU issue of the step from the committed SQ counter record (taken on
+    the current kernel sources and launch shape), against the issue peak."""
+    path = VALU_FILE.format(workload=workload, dtype=dtype)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash() or t.get("launch") != launch:
+        return None
+    per_s = t["sq_insts_valu_per_launch"] / (ms * 1e-3)
+    return {"wave_instructions_per_launch": t["sq_insts_valu_per_launch"],
+            "fp64_wave_instructions_per_launch": t["sq_insts_valu_fp64_per_launch"],
+            "achieved_per_s": per_s, "peak_per_s": VALU_PEAK_WAVE_INSTS,
+            "frac": per_s / VALU_PEAK_WAVE_INSTS, "source": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(wl, u, budget_s=20.0):
@@ -427,7 +448,10 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_step,
                      "bytes_per_node": bytes_step / wl.n_nodes,
                      "touched_grid_points": touched,
-                     "traffic_source": traffic_src},
+                     "traffic_source": traffic_src,
+                     # what bounds the step: VALU issue (SQ counters of the same
+                     # kernel, committed beside the traffic record)
+                     "valu_issue": load_valu(wl.name, args.precision, launch, ms)},
     }
     if tuning is not None:
         out["autotune"] = [{"options": r["options"], "ms": r["ms"], "units": r["units"],
