@@ -71,6 +71,9 @@ def lib():
         L.orc_spread_mls.argtypes = [C.c_int64, d, d, d, C.c_int, C.c_int, C.c_int, C.c_double,
                                      C.c_double, d]
         L.orc_centroid_to_nodes.argtypes = [C.c_int64, C.c_int64, i32, d, d]
+        L.orc_direct_forcing_mls.restype = C.c_int
+        L.orc_direct_forcing_mls.argtypes = [C.c_int64, d, d, d, C.c_int, C.c_int, C.c_int,
+                                             C.c_double, C.c_double, d, C.c_double, d, d]
         _lib = L
     return _lib
 
@@ -370,3 +373,19 @@ def centroid_to_nodes(m, Fc):
     lib().orc_centroid_to_nodes(N, len(fa), _p(fa, C.c_int32), _p(_f64(Fc), C.c_double),
                                 _p(Fn, C.c_double))
     return Fn
+
+
+def direct_forcing_mls(P, Am, Vb, grid, u, alpha, dt, f=None):
+    """Direct forcing at the markers: Fm = (Vb - MLS interp of u) / dt, and
+    f += MLS spreading of Fm.  Returns (Fm, f)."""
+    P = _f64(P)
+    nx, ny, nz, h = _grid(grid)
+    if f is None:
+        f = np.zeros((3, nz, ny, nx))
+    Fm = np.zeros((len(P), 3))
+    bad = lib().orc_direct_forcing_mls(len(P), _p(P, C.c_double), _p(_f64(Am), C.c_double),
+                                       _p(_f64(Vb), C.c_double), nx, ny, nz, h, float(alpha),
+                                       _p(_f64(u), C.c_double), float(dt), _p(Fm, C.c_double),
+                                       _p(f, C.c_double))
+    assert bad == 0, f"{bad} singular moment matrices"
+    return Fm, f

@@ -198,3 +198,54 @@ def test_centroid_forces_to_vertices():
     Fc = np.random.default_rng(7).normal(size=(len(f), 3))
     Fn = O.centroid_to_nodes(M, Fc)
     assert np.abs(Fn.sum(0) - Fc.sum(0)).max() <= 1e-12
+
+
+def test_direct_forcing_vanishes_when_the_fluid_follows():
+    """Direct forcing F = (V^b - U)/dt is zero (up to rounding) when the
+    velocity field is a linear field and the markers' desired velocity is that
+    field at the markers: MLS reproduces it exactly, and nothing is spread."""
+    rng = np.random.default_rng(8)
+    g = grid()
+    P = markers(rng, g)
+    Am = rng.uniform(0.5, 2.0, size=len(P)) * g.h ** 2
+    a = rng.normal(size=3)
+    b = rng.normal(size=(3, 3))
+    u = np.stack([a[d] + lattice_points(g, d) @ b[d] for d in range(3)])
+    Vb = a[None, :] + P @ b.T
+    Fm, f = O.direct_forcing_mls(P, Am, Vb, g, u, 0.4, 1e-3)
+    assert np.abs(Fm).max() <= 1e-9 and np.abs(f).max() <= 1e-9 * (len(P) / g.h ** 2)
+
+
+def test_direct_forcing_force_and_composition():
+    """With a random field: Fm = (Vb - U)/dt with U the interpolation, and the
+    total spread force equals sum_l A_l h Fm_l (force conservation)."""
+    rng = np.random.default_rng(9)
+    g = grid()
+    P = markers(rng, g)
+    Am = rng.uniform(0.5, 2.0, size=len(P)) * g.h ** 2
+    u = rng.normal(size=(3, g.nz, g.ny, g.nx))
+    Vb = rng.normal(size=(len(P), 3))
+    dt = 2e-3
+    Fm, f = O.direct_forcing_mls(P, Am, Vb, g, u, 0.5, dt)
+    U = O.interp_mls(P, g, u, 0.5)
+    assert np.abs(Fm - (Vb - U) / dt).max() <= 1e-12 * np.abs(Fm).max()
+    tot = f.reshape(3, -1).sum(axis=1) * g.h ** 3
+    want = ((Am * g.h)[:, None] * Fm).sum(axis=0)
+    assert np.abs(tot - want).max() <= 1e-12 * np.abs((Am * g.h)[:, None] * Fm).sum()
+
+
+def test_direct_forcing_body_moving_through_still_fluid():
+    """Closed form: with the fluid at rest (u = 0) and every marker asked to
+    move at V, the force is V/dt at every marker and the total force given to
+    the fluid is sum_l A_l h V / dt, along V."""
+    rng = np.random.default_rng(10)
+    g = grid()
+    P = markers(rng, g)
+    Am = rng.uniform(0.5, 2.0, size=len(P)) * g.h ** 2
+    V = np.array([0.3, -0.2, 0.5])
+    dt = 1e-2
+    u = np.zeros((3, g.nz, g.ny, g.nx))
+    Fm, f = O.direct_forcing_mls(P, Am, np.tile(V, (len(P), 1)), g, u, 0.4, dt)
+    assert np.abs(Fm - V / dt).max() <= 1e-14 * np.abs(V / dt).max()
+    tot = f.reshape(3, -1).sum(axis=1) * g.h ** 3
+    assert np.abs(tot - Am.sum() * g.h * V / dt).max() <= 1e-12 * np.abs(Am.sum() * g.h * V / dt).max()
