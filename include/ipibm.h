@@ -238,6 +238,17 @@ ip_status ibm_interp_mls(ip_plan *plan, const double *X, const void *u, double a
 ip_status ibm_spread_mls(ip_plan *plan, const double *X, const void *Fm, double alpha, void *f,
                          void *stream);
 
+/* Direct-forcing immersed-boundary force at the centroid markers (Section
+ * 2.2): F_l = (Vb_l - U_l) / dt, with U_l the MLS interpolation of u at the
+ * centroid of face l (as ibm_interp_mls) and Vb_l the desired velocity of the
+ * marker; F is spread to f with the same shape functions and the factor c_l
+ * (as ibm_spread_mls), in one pass that computes each marker's shape
+ * functions once.  Vb: real[F][3]; u: real[3][nz][ny][nx]; Fm: real[F][3]
+ * receives F (may be NULL); f: real[3][nz][ny][nx], ACCUMULATED (caller
+ * zeroes it), device atomics.  alpha and dt positive and finite. */
+ip_status ibm_direct_forcing_mls(ip_plan *plan, const double *X, const void *Vb, const void *u,
+                                 double alpha, double dt, void *Fm, void *f, void *stream);
+
 /* Centroid forces to the vertices (Section 2.3): Fn[n] = (1/3) sum of Fc[f]
  * over the faces f of vertex n.  Fc: real[F][3]; Fn: real[N][3]
  * (overwritten).  A gather over the plan's per-node lists: no atomics,

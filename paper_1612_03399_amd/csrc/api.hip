@@ -462,6 +462,19 @@ ip_status ibm_spread_mls(ip_plan *plan, const double *X, const void *Fm, double 
     return launch_spread_mls(plan, X, Fm, alpha, f, (hipStream_t)stream);
 }
 
+ip_status ibm_direct_forcing_mls(ip_plan *plan, const double *X, const void *Vb, const void *u,
+                                 double alpha, double dt, void *Fm, void *f, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return arg_error("alpha must be positive and finite");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return arg_error("dt must be positive and finite");
+    if (plan->F > 0 && (!X || !Vb || !u || !f)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(Vb, plan->real_size()) || !aligned(u, plan->real_size()) ||
+        !aligned(Fm, plan->real_size()) || !aligned(f, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_direct_forcing_mls(plan, X, Vb, u, alpha, dt, Fm, f, (hipStream_t)stream);
+}
+
 ip_status ip_centroid_to_nodes(ip_plan *plan, const void *Fc, void *Fn, void *stream) {
     IP_TRY(check_plan(plan));
     if (plan->N > 0 && (!Fn || (plan->F > 0 && !Fc))) return arg_error("NULL array");

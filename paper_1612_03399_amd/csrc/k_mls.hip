@@ -181,6 +181,54 @@ __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
 
+// Direct forcing, one thread per marker (plans without work units):
+// F = (V^b - U) / dt at the centroid, stored to Fout when given, spread with
+// device atomics.
+template <typename R>
+__global__ __launch_bounds__(256) void k_direct_forcing_mls(
+    const double *__restrict__ X, const int32_t *__restrict__ faces, int64_t F,
+    const R *__restrict__ u, const R *__restrict__ Vb, MlsGrid g, double inv_alpha,
+    double inv_dt, R *__restrict__ Fout, R *__restrict__ fld, uint32_t *status) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    double area;
+    const vec3<double> x = centroid(X, faces, f, area);
+    bool bad = false;
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        MlsShape S;
+        bad |= !mls_shape(x, d, g, inv_alpha, S);
+        const R *ud = u + d * g.field;
+        double U = 0.0, sphi = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const R *row = ud + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double ph = mls_phi(S, i, j, k);
+                    U += ph * (double)row[S.idx[0][i]];
+                    sphi += ph;
+                }
+            }
+        const double Fl = ((double)Vb[3 * f + d] - U) * inv_dt;
+        if (Fout != nullptr) Fout[3 * f + d] = (R)Fl;
+        const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
+        const double Fd = Fl * area * hl / (sphi * g.h * g.h * g.h);
+        R *fd = fld + d * g.field;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                R *row = fd + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) unsafeAtomicAdd(row + S.idx[0][i], (R)(mls_phi(S, i, j, k) * Fd));
+            }
+    }
+    if (bad) atomicOr(status, IP_STATUS_NONFINITE);
+}
+
 // The centroid's cell (the stencil centre of the lattices staggered by half a
 // cell, as the fused step's tile uses): the supports of all three lattices lie
 // in points cell - 1 .. cell + 2 per axis.
@@ -198,7 +246,10 @@ __device__ __forceinline__ vec3<double> marker_of(const double *xs, const uint16
 
 struct MlsUnitArgs {
     const double *X;
-    const void *Fm;
+    const void *Fm;          // marker forces (spreading)
+    const void *u, *Vb;      // velocity field and desired marker velocity (direct forcing)
+    void *Fout;              // marker forces written by direct forcing (may be NULL)
+    double inv_dt;
     void *f;
     MlsGrid g;
     double inv_alpha;
@@ -211,7 +262,10 @@ struct MlsUnitArgs {
 };
 
 // Spreading of the faces owned by one work unit (one workgroup per unit).
-template <typename R, int NT>
+// DF (direct forcing): the marker force is F = (V^b - U) / dt with U
+// interpolated from u with the same shape functions, stored to Fout when
+// given, then spread.
+template <typename R, int NT, bool DF>
 __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[NT / 64];
@@ -302,7 +356,25 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
                     for (int i = 0; i < 3; ++i) sphi += mls_phi(S, i, j, k);
             const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
             const double cl = area * hl / (sphi * g.h * g.h * g.h);
-            const double Fd = (double)Fm[3 * (int64_t)a.frec_perm[f0 + t] + d] * cl;
+            const int64_t pf = a.frec_perm[f0 + t];
+            double Fl;
+            if constexpr (DF) {
+                const R *ud = (const R *)a.u + d * g.field;
+                double U = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const R *row = ud + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) U += mls_phi(S, i, j, k) * (double)row[S.idx[0][i]];
+                    }
+                Fl = ((double)((const R *)a.Vb)[3 * pf + d] - U) * a.inv_dt;
+                if (a.Fout != nullptr) ((R *)a.Fout)[3 * pf + d] = (R)Fl;
+            } else {
+                Fl = (double)Fm[3 * pf + d];
+            }
+            const double Fd = Fl * cl;
             // support point c - 1 + j is tile point c + j - lo (inside the tile
             // for every marker the box was taken from; checked all the same)
             const int ox = S.c[0] - lo[0], oy = S.c[1] - lo[1], oz = S.c[2] - lo[2];
@@ -433,14 +505,14 @@ ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double 
         IP_TRY(unit_args(p, X, alpha, a, lds));
         a.Fm = Fm;
         a.f = f;
-        const void *fn = p->prec == IP_F64 ? (const void *)k_spread_mls_units<double, kMlsThreads>
-                                           : (const void *)k_spread_mls_units<float, kMlsThreads>;
+        const void *fn = p->prec == IP_F64 ? (const void *)k_spread_mls_units<double, kMlsThreads, false>
+                                           : (const void *)k_spread_mls_units<float, kMlsThreads, false>;
         IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         if (p->prec == IP_F64)
-            hipLaunchKernelGGL((k_spread_mls_units<double, kMlsThreads>), dim3(p->n_units),
+            hipLaunchKernelGGL((k_spread_mls_units<double, kMlsThreads, false>), dim3(p->n_units),
                                dim3(kMlsThreads), lds, s, a);
         else
-            hipLaunchKernelGGL((k_spread_mls_units<float, kMlsThreads>), dim3(p->n_units),
+            hipLaunchKernelGGL((k_spread_mls_units<float, kMlsThreads, false>), dim3(p->n_units),
                                dim3(kMlsThreads), lds, s, a);
         IP_HIP_CHECK(hipGetLastError());
         return IP_OK;
@@ -452,6 +524,44 @@ ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double 
     else
         hipLaunchKernelGGL(k_spread_mls<float>, grid, block, 0, s, X, p->faces, p->F,
                            (const float *)Fm, g, 1.0 / alpha, (float *)f, p->status);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
+
+ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb, const void *u,
+                                    double alpha, double dt, void *Fout, void *f, hipStream_t s) {
+    if (p->F == 0) return IP_OK;
+    const MlsGrid g = mls_grid(p);
+    if (p->fused_all && p->n_units > 0) {
+        MlsUnitArgs a{};
+        size_t lds = 0;
+        IP_TRY(unit_args(p, X, alpha, a, lds));
+        a.u = u;
+        a.Vb = Vb;
+        a.Fout = Fout;
+        a.inv_dt = 1.0 / dt;
+        a.f = f;
+        const void *fn = p->prec == IP_F64 ? (const void *)k_spread_mls_units<double, kMlsThreads, true>
+                                           : (const void *)k_spread_mls_units<float, kMlsThreads, true>;
+        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        if (p->prec == IP_F64)
+            hipLaunchKernelGGL((k_spread_mls_units<double, kMlsThreads, true>), dim3(p->n_units),
+                               dim3(kMlsThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_spread_mls_units<float, kMlsThreads, true>), dim3(p->n_units),
+                               dim3(kMlsThreads), lds, s, a);
+        IP_HIP_CHECK(hipGetLastError());
+        return IP_OK;
+    }
+    const dim3 grid(nblocks(p->F, 256)), block(256);
+    if (p->prec == IP_F64)
+        hipLaunchKernelGGL(k_direct_forcing_mls<double>, grid, block, 0, s, X, p->faces, p->F,
+                           (const double *)u, (const double *)Vb, g, 1.0 / alpha, 1.0 / dt,
+                           (double *)Fout, (double *)f, p->status);
+    else
+        hipLaunchKernelGGL(k_direct_forcing_mls<float>, grid, block, 0, s, X, p->faces, p->F,
+                           (const float *)u, (const float *)Vb, g, 1.0 / alpha, 1.0 / dt,
+                           (float *)Fout, (float *)f, p->status);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }

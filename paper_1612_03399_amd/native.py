@@ -84,6 +84,7 @@ def _load():
         "ibm_interp_mls": [vp, vp, vp, d, vp, vp],
         "ibm_spread_mls": [vp, vp, vp, d, vp, vp],
         "ip_centroid_to_nodes": [vp, vp, vp, vp],
+        "ibm_direct_forcing_mls": [vp, vp, vp, vp, d, d, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -269,6 +270,18 @@ def ibm_spread_mls(plan: Plan, X, Fm, alpha, f, stream=None):
     _check(LIB.ibm_spread_mls(plan.handle, _ptr(X), _ptr(Fm), float(alpha), _ptr(f),
                               _stream(stream)))
     return f
+
+
+def ibm_direct_forcing_mls(plan: Plan, X, Vb, u, alpha, dt, f, Fm=None, stream=None):
+    """Direct forcing at the face centroids: Fm = (Vb - U)/dt with U the MLS
+    interpolation of u, spread into f (accumulated).  Returns (Fm, f); pass
+    Fm=False to skip storing the marker forces."""
+    if Fm is None:
+        Fm = torch.empty(plan.F, 3, dtype=plan.dtype, device=X.device)
+    fm = None if Fm is False else Fm
+    _check(LIB.ibm_direct_forcing_mls(plan.handle, _ptr(X), _ptr(Vb), _ptr(u), float(alpha),
+                                      float(dt), _ptr(fm), _ptr(f), _stream(stream)))
+    return fm, f
 
 
 def ip_centroid_to_nodes(plan: Plan, Fc, Fn=None, stream=None):

@@ -117,3 +117,50 @@ def test_mls_full_size_sampled():
     e_c = np.abs(tot - want).max() / scale.max()
     say(f"  U sampled {e_u:.2e}  conservation {e_c:.2e}")
     assert e_u <= TOL["f64"] and e_c <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_direct_forcing_parity(case, precision):
+    """ibm_direct_forcing_mls against the oracle: the marker forces
+    (Vb - U)/dt and the spread field, in one pass on the GPU."""
+    say("direct forcing", case, precision)
+    wl = CASES[case]()
+    rdt = N.real_dtype(precision)
+    rng = np.random.default_rng(12)
+    u, _ = inputs(wl, precision)
+    Vb = rng.normal(scale=0.1, size=(wl.n_faces, 3))
+    if precision == "f32":
+        Vb = Vb.astype(np.float32).astype(np.float64)
+    alpha, dt = 0.4, 1e-3
+    Cc, Af = O.centroids(wl, wl.X)
+    Fm_want, f_want = O.direct_forcing_mls(Cc, Af, Vb, wl.grid, u, alpha, dt)
+    plan = N.Plan(wl, wl.grid, precision)
+    X = dev(wl.X)
+    f = torch.zeros(u.shape, dtype=rdt, device=DEV)
+    Fm, _ = N.ibm_direct_forcing_mls(plan, X, dev(Vb, rdt), dev(u, rdt), alpha, dt, f)
+    f2 = torch.zeros_like(f)
+    none, _ = N.ibm_direct_forcing_mls(plan, X, dev(Vb, rdt), dev(u, rdt), alpha, dt, f2, Fm=False)
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    assert none is None
+    e_m = rel_inf(host(Fm).astype(np.float64), Fm_want)
+    e_f = rel_inf(host(f).astype(np.float64), f_want)
+    e_f2 = rel_inf(host(f2).astype(np.float64), f_want)
+    say(f"  Fm {e_m:.2e}  f {e_f:.2e}  f (no Fm) {e_f2:.2e}")
+    # F = (Vb - U)/dt: the rounding of U relative to |U| is amplified by
+    # |U| / |Vb - U| at most, which the tolerance on Fm allows for
+    amp = max(1.0, np.abs(u).max() / np.abs(Vb - 0).max())
+    assert e_m <= TOL[precision] * amp and e_f <= TOL[precision] * amp and e_f2 <= TOL[precision] * amp
+
+
+def test_direct_forcing_rejects_bad_dt():
+    wl = CASES["drop_L3_64"]()
+    plan = N.Plan(wl, wl.grid, "f64")
+    X = dev(wl.X)
+    u = dev(wl.velocity())
+    Vb = torch.zeros(wl.n_faces, 3, dtype=torch.float64, device=DEV)
+    f = torch.zeros_like(u)
+    for dt in (0.0, -1e-3, float("nan")):
+        with pytest.raises(N.IpibmError):
+            N.ibm_direct_forcing_mls(plan, X, Vb, u, 0.4, dt, f)
