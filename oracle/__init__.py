@@ -71,6 +71,9 @@ def lib():
         L.orc_spread_mls.argtypes = [C.c_int64, d, d, d, C.c_int, C.c_int, C.c_int, C.c_double,
                                      C.c_double, d]
         L.orc_centroid_to_nodes.argtypes = [C.c_int64, C.c_int64, i32, d, d]
+        L.orc_probe_loads.restype = C.c_int
+        L.orc_probe_loads.argtypes = [C.c_int, i64, u8, i32, d, C.c_int, C.c_int, C.c_int,
+                                      C.c_double, C.c_double, d, d, d, C.c_double, d]
         L.orc_direct_forcing_mls.restype = C.c_int
         L.orc_direct_forcing_mls.argtypes = [C.c_int64, d, d, d, C.c_int, C.c_int, C.c_int,
                                              C.c_double, C.c_double, d, C.c_double, d, d]
@@ -389,3 +392,22 @@ def direct_forcing_mls(P, Am, Vb, grid, u, alpha, dt, f=None):
                                        _p(f, C.c_double))
     assert bad == 0, f"{bad} singular moment matrices"
     return Fm, f
+
+
+def probe_loads(m, X, grid, u, p, alpha, mu, acc=None):
+    """External loads Fext[F][3] on every face from normal probes of length h:
+    pressure (cell-centred field p[nz][ny][nx]) and viscous stress mu (G + G^T)
+    from the MLS fits at the probe ends; one probe on closed bodies, two on
+    open ones; acc[F][3] the marker acceleration (None: zero)."""
+    fo = np.ascontiguousarray(m.face_off, np.int64)
+    fa = np.ascontiguousarray(m.faces, np.int32)
+    cl = np.ascontiguousarray(m.closed, np.uint8)
+    nx, ny, nz, h = _grid(grid)
+    Fext = np.zeros((len(fa), 3))
+    bad = lib().orc_probe_loads(len(fo) - 1, _p(fo, C.c_int64), _p(cl, C.c_uint8),
+                                _p(fa, C.c_int32), _p(_f64(X), C.c_double), nx, ny, nz, h,
+                                float(alpha), _p(_f64(u), C.c_double), _p(_f64(p), C.c_double),
+                                None if acc is None else _p(_f64(acc), C.c_double), float(mu),
+                                _p(Fext, C.c_double))
+    assert bad == 0, f"{bad} singular moment matrices"
+    return Fext

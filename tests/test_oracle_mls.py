@@ -249,3 +249,97 @@ def test_direct_forcing_body_moving_through_still_fluid():
     assert np.abs(Fm - V / dt).max() <= 1e-14 * np.abs(V / dt).max()
     tot = f.reshape(3, -1).sum(axis=1) * g.h ** 3
     assert np.abs(tot - Am.sum() * g.h * V / dt).max() <= 1e-12 * np.abs(Am.sum() * g.h * V / dt).max()
+
+
+# ---- external loads by normal probes (Section 2.2) -------------------------
+
+class _Mesh:
+    pass
+
+
+def sphere_mesh(g, level=2, r=0.2):
+    """A closed icosphere of radius r at the box centre (probes stay away from
+    the periodic seam)."""
+    v, f = W.icosphere(level)
+    m = _Mesh()
+    L = g.nx * g.h
+    m.X = 0.5 * L + r * v
+    m.faces = np.asarray(f, np.int32)
+    m.face_off = np.array([0, len(f)])
+    m.closed = np.array([1], np.uint8)
+    return m
+
+
+def sheet_mesh(g, tilt=0.3):
+    """An open, tilted flat sheet through the box centre."""
+    st, f = W.flat_patch(6, 5, 0.3, 0.25)
+    L = g.nx * g.h
+    e1 = np.array([1.0, 0.2, -0.1])
+    e1 /= np.linalg.norm(e1)
+    e2 = np.array([0.1, 1.0, tilt])
+    e2 -= (e2 @ e1) * e1
+    e2 /= np.linalg.norm(e2)
+    m = _Mesh()
+    m.X = 0.35 * L + st[:, :1] * e1 + st[:, 1:] * e2
+    m.faces = f
+    m.face_off = np.array([0, len(f)])
+    m.closed = np.array([0], np.uint8)
+    return m
+
+
+def face_geometry(m):
+    Cc, Af = O.centroids(m, m.X)
+    n = np.cross(m.X[m.faces[:, 1]] - m.X[m.faces[:, 0]], m.X[m.faces[:, 2]] - m.X[m.faces[:, 0]])
+    return Cc, Af, n / np.linalg.norm(n, axis=1, keepdims=True)
+
+
+def cell_centres(g):
+    k, j, i = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    return np.stack([(i + 0.5) * g.h, (j + 0.5) * g.h, (k + 0.5) * g.h], axis=-1)
+
+
+def test_probe_loads_shear_flow():
+    """Simple shear u_x = gamma y, no pressure: the MLS fit of a linear field is
+    exact, so every face carries tau n A with tau_xy = tau_yx = mu gamma, i.e.
+    mu gamma (n_y, n_x, 0) A, and the total over a closed surface vanishes."""
+    g = grid(32, 1.0 / 32)
+    m = sphere_mesh(g)
+    gamma, mu = 1.7, 0.3
+    u = np.zeros((3, g.nz, g.ny, g.nx))
+    u[0] = gamma * lattice_points(g, 0)[..., 1]
+    F = O.probe_loads(m, m.X, g, u, np.zeros((g.nz, g.ny, g.nx)), 0.4, mu)
+    _, Af, n = face_geometry(m)
+    want = mu * gamma * np.stack([n[:, 1], n[:, 0], np.zeros(len(n))], axis=1) * Af[:, None]
+    assert np.abs(F - want).max() <= 1e-12 * np.abs(want).max()
+    assert np.abs(F.sum(axis=0)).max() <= 1e-12 * np.abs(want).sum()
+
+
+def test_probe_loads_linear_pressure_closed():
+    """Pressure p = p0 + g.x at the cell centres, fluid at rest: each face of a
+    closed body carries -p(x_c + h n) n A (the outward probe end), with the
+    marker acceleration adding -h (a.n) n A."""
+    g = grid(32, 1.0 / 32)
+    m = sphere_mesh(g)
+    p0, gv = 2.0, np.array([0.5, -1.0, 0.8])
+    pr = p0 + cell_centres(g) @ gv
+    acc = np.random.default_rng(11).normal(size=(len(m.faces), 3))
+    F = O.probe_loads(m, m.X, g, np.zeros((3, g.nz, g.ny, g.nx)), pr, 0.4, 0.7, acc)
+    Cc, Af, n = face_geometry(m)
+    pe = p0 + (Cc + g.h * n) @ gv + g.h * (acc * n).sum(axis=1)
+    want = -pe[:, None] * n * Af[:, None]
+    assert np.abs(F - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_probe_loads_open_sheet_two_sided():
+    """An open sheet probes both sides: with a linear pressure and a marker
+    acceleration a, p+ - p- = 2 h (g + a).n and the load is -2 h ((g + a).n) n A."""
+    g = grid(32, 1.0 / 32)
+    m = sheet_mesh(g)
+    gv = np.array([0.5, -1.0, 0.8])
+    pr = 3.0 + cell_centres(g) @ gv
+    acc = np.random.default_rng(12).normal(size=(len(m.faces), 3))
+    F = O.probe_loads(m, m.X, g, np.zeros((3, g.nz, g.ny, g.nx)), pr, 0.4, 0.7, acc)
+    _, Af, n = face_geometry(m)
+    jump = 2.0 * g.h * ((gv[None, :] + acc) * n).sum(axis=1)
+    want = -jump[:, None] * n * Af[:, None]
+    assert np.abs(F - want).max() <= 1e-12 * np.abs(want).max()
