@@ -45,14 +45,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def touched_points(X, grid):
+MAC_OFFSETS = ((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
+
+
+def touched_points(X, grid, offsets=MAC_OFFSETS):
     """Number of distinct (lattice, point) pairs in the union of all nodes'
-    3x3x3 supports (what interpolation reads and spreading updates)."""
+    3x3x3 supports (what interpolation reads and spreading updates) over the
+    lattices with the given offsets (in cells; default the three MAC ones)."""
     total = 0
     n = np.array([grid.nx, grid.ny, grid.nz], np.int64)
-    for d in range(3):
-        off = np.array([0.5, 0.5, 0.5])
-        off[d] = 0.0
+    for off in offsets:
+        off = np.asarray(off, np.float64)
         c = np.floor(X / grid.h - off + 0.5).astype(np.int64)
         keys = []
         for dz in (-1, 0, 1):
@@ -283,7 +286,8 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
 
 def mls_leg(N, W, bodies, dev, torch, log, reps=20, alpha=0.4):
     """MLS transfer at the triangle centroids on the same batch (one marker per
-    face): ibm_interp_mls and ibm_spread_mls timed with HIP events on the launch
+    face): ibm_interp_mls, ibm_spread_mls, ibm_direct_forcing_mls and
+    ibm_probe_loads timed with HIP events on the launch
     stream, and their algorithmic bytes: vertex positions read once, face
     indices, the marker values, and the grid values in the union of the
     markers' 27-point supports (u read; f read and written)."""
@@ -318,16 +322,35 @@ def mls_leg(N, W, bodies, dev, torch, log, reps=20, alpha=0.4):
     Vb = torch.zeros_like(Fm)
     t_d = timed(lambda: N.ibm_direct_forcing_mls(plan, X, Vb, u, alpha, 1e-4, f, Fm=U,
                                                  stream=stream))
+    # external loads by normal probes: pressure at cell centres, mu = 1e-3
+    p = (torch.rand((wl.grid.nz, wl.grid.ny, wl.grid.nx), generator=g, device=dev,
+                    dtype=torch.float64) - 0.5)
+    acc = torch.rand((wl.n_faces, 3), generator=g, device=dev, dtype=torch.float64) - 0.5
+    t_p = timed(lambda: N.ibm_probe_loads(plan, X, u, p, alpha, 1e-3, acc=acc, Fext=U,
+                                          stream=stream))
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags} in the mls leg")
     fa = np.asarray(wl.faces)
     cen = (wl.X[fa[:, 0]] + wl.X[fa[:, 1]] + wl.X[fa[:, 2]]) / 3.0
     touched = touched_points(cen, wl.grid)
+    nrm = np.cross(wl.X[fa[:, 1]] - wl.X[fa[:, 0]], wl.X[fa[:, 2]] - wl.X[fa[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    ends = [cen + wl.grid.h * nrm]
+    closed = np.repeat(np.asarray(wl.closed, bool), np.diff(np.asarray(wl.face_off)))
+    if not closed.all():
+        ends.append(cen[~closed] - wl.grid.h * nrm[~closed])
+    ends = np.concatenate(ends)
+    touched_p = touched_points(ends, wl.grid, MAC_OFFSETS + ((0.5, 0.5, 0.5),))
     common = wl.n_nodes * 24 + wl.n_faces * 12
     b_i = common + wl.n_faces * 24 + touched * 8
     b_s = common + wl.n_faces * 24 + touched * 16
+    # probes: positions, faces, acc read and Fext written per face, u and p
+    # over the union of the probe ends' supports
+    b_p = common + wl.n_faces * 48 + touched_p * 8
     out = {"mls_markers": wl.n_faces, "mls_alpha": alpha,
+           "probe_loads_ms": t_p, "probe_loads_algorithmic_bytes": b_p,
+           "probe_loads_hbm_frac": b_p / (t_p * 1e-3) / (HBM_PEAK_GBS * 1e9),
            "mls_interp_ms": t_i, "mls_spread_ms": t_s, "mls_direct_forcing_ms": t_d,
            "mls_interp_markers_per_s": wl.n_faces / (t_i * 1e-3),
            "mls_interp_algorithmic_bytes": b_i, "mls_spread_algorithmic_bytes": b_s,
@@ -335,8 +358,9 @@ def mls_leg(N, W, bodies, dev, torch, log, reps=20, alpha=0.4):
            "mls_spread_hbm_frac": b_s / (t_s * 1e-3) / (HBM_PEAK_GBS * 1e9)}
     log(f"mls: interp {t_i:.3f} ms ({out['mls_interp_hbm_frac']:.1%} of HBM), "
         f"spread {t_s:.3f} ms ({out['mls_spread_hbm_frac']:.1%}), "
-        f"direct forcing in one pass {t_d:.3f} ms (interp + spread {t_i + t_s:.3f} ms)")
-    del plan, u, f, Fm, U, X, Vb
+        f"direct forcing in one pass {t_d:.3f} ms (interp + spread {t_i + t_s:.3f} ms), "
+        f"probe loads {t_p:.3f} ms ({out['probe_loads_hbm_frac']:.1%})")
+    del plan, u, f, Fm, U, X, Vb, p, acc
     torch.cuda.empty_cache()
     return out
 

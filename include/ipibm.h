@@ -249,6 +249,23 @@ ip_status ibm_spread_mls(ip_plan *plan, const double *X, const void *Fm, double 
 ip_status ibm_direct_forcing_mls(ip_plan *plan, const double *X, const void *Vb, const void *u,
                                  double alpha, double dt, void *Fm, void *f, void *stream);
 
+/* External (hydrodynamic) loads on the faces by normal probes (Section 2.2).
+ * From each face centroid x_c a probe of length h runs along the unit normal
+ * n (counter-clockwise corner order seen from outside): one outward probe on
+ * closed bodies, one on each side of open ones.  At a probe end y = x_c + s h n
+ * (s = +1 or -1): p = P(y) + s h acc.n with P the MLS value of the
+ * cell-centred pressure (lattice points at cell centres), G_ij = du_i/dx_j
+ * the gradient of the MLS linear fit of lattice i at y, tau = mu (G + G^T);
+ * Fext = sum over the probes of s (-p n + tau n) A_f (for an open body, the
+ * jump -(p+ - p-) n + (tau+ - tau-) n).  Readings of the paper: the probe
+ * length is h (the mean local grid size of a uniform grid); the velocity
+ * gradient is that of the local MLS linear fit; the acceleration correction
+ * carries the probe's side s.  u: real[3][nz][ny][nx]; p: real[nz][ny][nx];
+ * acc: real[F][3] marker acceleration Du/Dt (may be NULL: zero); Fext:
+ * real[F][3] (overwritten).  alpha positive, mu >= 0, both finite. */
+ip_status ibm_probe_loads(ip_plan *plan, const double *X, const void *u, const void *p,
+                          const void *acc, double alpha, double mu, void *Fext, void *stream);
+
 /* Centroid forces to the vertices (Section 2.3): Fn[n] = (1/3) sum of Fc[f]
  * over the faces f of vertex n.  Fc: real[F][3]; Fn: real[N][3]
  * (overwritten).  A gather over the plan's per-node lists: no atomics,

@@ -475,6 +475,19 @@ ip_status ibm_direct_forcing_mls(ip_plan *plan, const double *X, const void *Vb,
     return launch_direct_forcing_mls(plan, X, Vb, u, alpha, dt, Fm, f, (hipStream_t)stream);
 }
 
+ip_status ibm_probe_loads(ip_plan *plan, const double *X, const void *u, const void *p,
+                          const void *acc, double alpha, double mu, void *Fext, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return arg_error("alpha must be positive and finite");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return arg_error("mu must be non-negative and finite");
+    if (plan->F > 0 && (!X || !u || !p || !Fext)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(u, plan->real_size()) || !aligned(p, plan->real_size()) ||
+        !aligned(acc, plan->real_size()) || !aligned(Fext, plan->real_size()))
+        return arg_error("misaligned array");
+    return launch_probe_loads(plan, X, u, p, acc, alpha, mu, Fext, (hipStream_t)stream);
+}
+
 ip_status ip_centroid_to_nodes(ip_plan *plan, const void *Fc, void *Fn, void *stream) {
     IP_TRY(check_plan(plan));
     if (plan->N > 0 && (!Fn || (plan->F > 0 && !Fc))) return arg_error("NULL array");

@@ -170,6 +170,8 @@ ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double a
 ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double alpha, void *f,
                             hipStream_t s);
 ip_status launch_centroid_to_nodes(ip_plan *p, const void *Fc, void *Fn, hipStream_t s);
+ip_status launch_probe_loads(ip_plan *p, const double *X, const void *u, const void *pr,
+                             const void *acc, double alpha, double mu, void *Fext, hipStream_t s);
 ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb, const void *u,
                                     double alpha, double dt, void *Fout, void *f, hipStream_t s);
 ip_status launch_update(ip_plan *p, double *X, const void *U, const void *F,

@@ -229,6 +229,146 @@ __global__ __launch_bounds__(256) void k_direct_forcing_mls(
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
 
+// MLS fit about y on a lattice with offsets off (cells): a = A^{-1} B q, the
+// linear fit q ~ a0 + a1 dx + a2 dy + a3 dz (offsets in units of h); a0 is
+// the MLS value at y and a1..a3 / h its gradient.  Returns false if the
+// solve is not finite.
+template <typename R>
+__device__ __forceinline__ bool mls_fit(const vec3<double> &y, const double off[3], const MlsGrid &g,
+                                        double inv_alpha, const R *__restrict__ q, double a[4]) {
+    const double ys[3] = {y.x, y.y, y.z};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    double w[3][3], dk[3][3], s0[3], s1[3], s2[3];
+    int idx[3][3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double s = ys[ax] * g.inv_h - off[ax];
+        double c = floor(s + 0.5);
+        if (!(fabs(c) < 1.0e9)) c = 0.0;
+        s0[ax] = s1[ax] = s2[ax] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double d = (c - 1.0 + j) - s;
+            const double r = fabs(d) * (1.0 / 1.5) * inv_alpha;
+            const double wj = fabs(d) <= 1.5 ? exp(-r * r) : 0.0;
+            w[ax][j] = wj;
+            dk[ax][j] = d;
+            idx[ax][j] = wrapi((int)c - 1 + j, n[ax]);
+            s0[ax] += wj;
+            s1[ax] += wj * d;
+            s2[ax] += wj * d * d;
+        }
+    }
+    // B q: weighted moments of the 27 values
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const R *row = q + (int64_t)idx[2][k] * g.plane + (int64_t)idx[1][j] * g.nx;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double wq = w[0][i] * w[1][j] * w[2][k] * (double)row[idx[0][i]];
+                m0 += wq;
+                m1 += wq * dk[0][i];
+                m2 += wq * dk[1][j];
+                m3 += wq * dk[2][k];
+            }
+        }
+    const double a00 = s0[0] * s0[1] * s0[2];
+    const double a01 = s1[0] * s0[1] * s0[2], a02 = s0[0] * s1[1] * s0[2], a03 = s0[0] * s0[1] * s1[2];
+    const double a11 = s2[0] * s0[1] * s0[2], a22 = s0[0] * s2[1] * s0[2], a33 = s0[0] * s0[1] * s2[2];
+    const double a12 = s1[0] * s1[1] * s0[2], a13 = s1[0] * s0[1] * s1[2], a23 = s0[0] * s1[1] * s1[2];
+    const double l00 = sqrt(a00);
+    const double l10 = a01 / l00, l20 = a02 / l00, l30 = a03 / l00;
+    const double l11 = sqrt(a11 - l10 * l10);
+    const double l21 = (a12 - l20 * l10) / l11, l31 = (a13 - l30 * l10) / l11;
+    const double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
+    const double l32 = (a23 - l30 * l20 - l31 * l21) / l22;
+    const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32);
+    const double y0 = m0 / l00;
+    const double y1 = (m1 - l10 * y0) / l11;
+    const double y2 = (m2 - l20 * y0 - l21 * y1) / l22;
+    const double y3 = (m3 - l30 * y0 - l31 * y1 - l32 * y2) / l33;
+    a[3] = y3 / l33;
+    a[2] = (y2 - l32 * a[3]) / l22;
+    a[1] = (y1 - l21 * a[2] - l31 * a[3]) / l11;
+    a[0] = (y0 - l10 * a[1] - l20 * a[2] - l30 * a[3]) / l00;
+    return isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]) && isfinite(a[3]);
+}
+
+// External loads on face f from probes of length h along its unit normal:
+// one outward probe on closed bodies, both sides on open ones.  At a probe
+// end y = x_c + s h n: p = (MLS value of the cell-centred pressure) +
+// s h (Du/Dt).n, G_ij = du_i/dx_j (gradient of the MLS fit of lattice i),
+// tau = mu (G + G^T); the load is sum_s s (-p n + tau n) A.
+template <typename R>
+__global__ __launch_bounds__(256) void k_probe_loads(
+    const double *__restrict__ X, const int32_t *__restrict__ faces,
+    const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
+    const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
+    double inv_alpha, double mu, R *__restrict__ Fext, uint32_t *status) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    // body of face f: the last b with face_off[b] <= f
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (face_off[mid] <= f)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const vec3<double> xa = ldX(X, faces[3 * f]), xb = ldX(X, faces[3 * f + 1]),
+                       xc3 = ldX(X, faces[3 * f + 2]);
+    const vec3<double> nn = cross(xb - xa, xc3 - xa);
+    const double nlen = sqrt(dot(nn, nn));
+    const double area = 0.5 * nlen;
+    const vec3<double> nu{nn.x / nlen, nn.y / nlen, nn.z / nlen};
+    const vec3<double> xc{(xa.x + xb.x + xc3.x) * (1.0 / 3.0), (xa.y + xb.y + xc3.y) * (1.0 / 3.0),
+                          (xa.z + xb.z + xc3.z) * (1.0 / 3.0)};
+    const double an = acc == nullptr ? 0.0
+                                     : (double)acc[3 * f] * nu.x + (double)acc[3 * f + 1] * nu.y +
+                                           (double)acc[3 * f + 2] * nu.z;
+    const double cc_off[3] = {0.5, 0.5, 0.5};
+    const int sides = closed[lo] ? 1 : 2;
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+    bool bad = !(nlen > 0.0);
+#pragma unroll 1
+    for (int side = 0; side < sides; ++side) {
+        const double sg = side == 0 ? 1.0 : -1.0;
+        const vec3<double> y{xc.x + sg * g.h * nu.x, xc.y + sg * g.h * nu.y, xc.z + sg * g.h * nu.z};
+        double ap[4], G[3][3];
+        bad |= !mls_fit<R>(y, cc_off, g, inv_alpha, pr, ap);
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {
+            const double off[3] = {mac_off(i, 0), mac_off(i, 1), mac_off(i, 2)};
+            double ai[4];
+            bad |= !mls_fit<R>(y, off, g, inv_alpha, u + i * g.field, ai);
+            G[i][0] = ai[1] * g.inv_h;
+            G[i][1] = ai[2] * g.inv_h;
+            G[i][2] = ai[3] * g.inv_h;
+        }
+        const double pl = ap[0] + sg * g.h * an;
+        const double n3[3] = {nu.x, nu.y, nu.z};
+        double Fs[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double tn = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) tn += mu * (G[i][j] + G[j][i]) * n3[j];
+            Fs[i] = sg * (-pl * n3[i] + tn) * area;
+        }
+        F0 += Fs[0];
+        F1 += Fs[1];
+        F2 += Fs[2];
+    }
+    Fext[3 * f] = (R)F0;
+    Fext[3 * f + 1] = (R)F1;
+    Fext[3 * f + 2] = (R)F2;
+    if (bad) atomicOr(status, IP_STATUS_NONFINITE);
+}
+
 // The centroid's cell (the stencil centre of the lattices staggered by half a
 // cell, as the fused step's tile uses): the supports of all three lattices lie
 // in points cell - 1 .. cell + 2 per axis.
@@ -562,6 +702,23 @@ ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb,
         hipLaunchKernelGGL(k_direct_forcing_mls<float>, grid, block, 0, s, X, p->faces, p->F,
                            (const float *)u, (const float *)Vb, g, 1.0 / alpha, 1.0 / dt,
                            (float *)Fout, (float *)f, p->status);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
+
+ip_status launch_probe_loads(ip_plan *p, const double *X, const void *u, const void *pr,
+                             const void *acc, double alpha, double mu, void *Fext, hipStream_t s) {
+    if (p->F == 0) return IP_OK;
+    const MlsGrid g = mls_grid(p);
+    const dim3 grid(nblocks(p->F, 256)), block(256);
+    if (p->prec == IP_F64)
+        hipLaunchKernelGGL(k_probe_loads<double>, grid, block, 0, s, X, p->faces, p->face_off,
+                           p->closed, p->B, p->F, (const double *)u, (const double *)pr,
+                           (const double *)acc, g, 1.0 / alpha, mu, (double *)Fext, p->status);
+    else
+        hipLaunchKernelGGL(k_probe_loads<float>, grid, block, 0, s, X, p->faces, p->face_off,
+                           p->closed, p->B, p->F, (const float *)u, (const float *)pr,
+                           (const float *)acc, g, 1.0 / alpha, mu, (float *)Fext, p->status);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }

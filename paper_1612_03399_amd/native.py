@@ -85,6 +85,7 @@ def _load():
         "ibm_spread_mls": [vp, vp, vp, d, vp, vp],
         "ip_centroid_to_nodes": [vp, vp, vp, vp],
         "ibm_direct_forcing_mls": [vp, vp, vp, vp, d, d, vp, vp, vp],
+        "ibm_probe_loads": [vp, vp, vp, vp, vp, d, d, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -282,6 +283,16 @@ def ibm_direct_forcing_mls(plan: Plan, X, Vb, u, alpha, dt, f, Fm=None, stream=N
     _check(LIB.ibm_direct_forcing_mls(plan.handle, _ptr(X), _ptr(Vb), _ptr(u), float(alpha),
                                       float(dt), _ptr(fm), _ptr(f), _stream(stream)))
     return fm, f
+
+
+def ibm_probe_loads(plan: Plan, X, u, p, alpha, mu, acc=None, Fext=None, stream=None):
+    """External loads Fext[F][3] on every face from normal probes (pressure
+    p[nz][ny][nx] at cell centres, velocity u, marker acceleration acc[F][3])."""
+    if Fext is None:
+        Fext = torch.empty(plan.F, 3, dtype=plan.dtype, device=X.device)
+    _check(LIB.ibm_probe_loads(plan.handle, _ptr(X), _ptr(u), _ptr(p), _ptr(acc), float(alpha),
+                               float(mu), _ptr(Fext), _stream(stream)))
+    return Fext
 
 
 def ip_centroid_to_nodes(plan: Plan, Fc, Fn=None, stream=None):

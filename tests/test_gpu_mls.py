@@ -1,7 +1,10 @@
 """GPU parity of the MLS transfer at the triangle centroids (ibm_interp_mls,
-ibm_spread_mls) and of the centroid-to-vertex transfer (ip_centroid_to_nodes)
+ibm_spread_mls, ibm_direct_forcing_mls), of the centroid-to-vertex transfer
+(ip_centroid_to_nodes) and of the probe loads (ibm_probe_loads)
 against the FP64 oracle, through the C-ABI: small cases element by element,
 the 1000-drop batch on sampled markers and by force conservation."""
+import types
+
 import numpy as np
 import pytest
 import torch
@@ -164,3 +167,67 @@ def test_direct_forcing_rejects_bad_dt():
     for dt in (0.0, -1e-3, float("nan")):
         with pytest.raises(N.IpibmError):
             N.ibm_direct_forcing_mls(plan, X, Vb, u, 0.4, dt, f)
+
+
+def probe_inputs(wl, precision, seed=21):
+    rng = np.random.default_rng(seed)
+    u = wl.velocity() + rng.normal(scale=0.05, size=(3, wl.grid.nz, wl.grid.ny, wl.grid.nx))
+    p = rng.normal(size=(wl.grid.nz, wl.grid.ny, wl.grid.nx))
+    acc = rng.normal(size=(wl.n_faces, 3))
+    if precision == "f32":
+        u, p, acc = (a.astype(np.float32).astype(np.float64) for a in (u, p, acc))
+    return u, p, acc
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_probe_loads_parity(case, precision):
+    """ibm_probe_loads against the oracle on closed drops and on the open
+    leaflets of the ventricle (two probes per face), with and without the
+    acceleration term."""
+    say("probe loads", case, precision)
+    wl = CASES[case]()
+    rdt = N.real_dtype(precision)
+    u, p, acc = probe_inputs(wl, precision)
+    alpha, mu = 0.4, 0.02
+    plan = N.Plan(wl, wl.grid, precision)
+    X = dev(wl.X)
+    for a in (acc, None):
+        want = O.probe_loads(wl, wl.X, wl.grid, u, p, alpha, mu, acc=a)
+        got = N.ibm_probe_loads(plan, X, dev(u, rdt), dev(p, rdt), alpha, mu,
+                                acc=None if a is None else dev(a, rdt))
+        code, flags = N.ip_plan_status(plan)
+        assert code == N.IP_OK, flags
+        e = rel_inf(host(got).astype(np.float64), want)
+        say(f"  acc {'yes' if a is not None else 'no'}: {e:.2e}")
+        assert e <= TOL[precision]
+
+
+def test_probe_loads_full_size_sampled():
+    """The 1000-drop batch: loads on 4000 sampled faces against the oracle
+    (run on those faces alone), in the launch the bench times."""
+    say("probe loads full size")
+    wl = W.config1()
+    u, p, acc = probe_inputs(wl, "f64")
+    plan = N.Plan(wl, wl.grid, "f64")
+    got = host(N.ibm_probe_loads(plan, dev(wl.X), dev(u), dev(p), 0.4, 1e-3, acc=dev(acc)))
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    pick = np.sort(np.random.default_rng(4).choice(wl.n_faces, 4000, replace=False))
+    sub = types.SimpleNamespace(faces=np.asarray(wl.faces)[pick], closed=[1],
+                                face_off=[0, pick.size])
+    want = O.probe_loads(sub, wl.X, wl.grid, u, p, 0.4, 1e-3, acc=acc[pick])
+    e = rel_inf(got[pick], want)
+    say(f"  sampled {e:.2e}")
+    assert e <= TOL["f64"]
+
+
+def test_probe_loads_rejects_bad_arguments():
+    wl = CASES["drop_L3_64"]()
+    plan = N.Plan(wl, wl.grid, "f64")
+    X = dev(wl.X)
+    u = dev(wl.velocity())
+    p = torch.zeros(u.shape[1:], dtype=torch.float64, device=DEV)
+    for alpha, mu in ((0.0, 0.1), (float("nan"), 0.1), (0.4, -1.0), (0.4, float("inf"))):
+        with pytest.raises(N.IpibmError):
+            N.ibm_probe_loads(plan, X, u, p, alpha, mu)
