@@ -48,14 +48,14 @@ def lib():
         L.orc_geometry.argtypes = [C.c_int, i64, i64, i32, d, d, d]
         L.orc_reference.argtypes = [C.c_int, i64, i64, i64, i32, i32, d, d, d, d, d]
         L.orc_forces.argtypes = [C.c_int, i64, i64, i64, i32, i32, u8, d, d, d, d, d, d,
-                                 d, d, d, d, d]
+                                 d, d, d, d, d, d]
         L.orc_forces_jvp.argtypes = [C.c_int, i64, i64, i64, i32, i32, u8, d, d, d, d, d, d,
-                                     d, d]
+                                     d, d, d]
         L.orc_interp.argtypes = [C.c_int64, d, C.c_int, C.c_int, C.c_int, C.c_double, d, d]
         L.orc_interp_jac.argtypes = [C.c_int64, d, C.c_int, C.c_int, C.c_int, C.c_double, d, d]
         L.orc_spread.argtypes = [C.c_int64, d, d, C.c_int, C.c_int, C.c_int, C.c_double, d]
         L.orc_step.argtypes = [C.c_int, i64, i64, i64, i32, i32, u8, u8, d, d, d, d, d, d, d,
-                               C.c_int, C.c_int, C.c_int, C.c_double, d, d, C.c_double,
+                               d, C.c_int, C.c_int, C.c_int, C.c_double, d, d, C.c_double,
                                d, d, d, d]
         L.orc_taylor.argtypes = [C.c_int, i64, d, d, d]
         L.orc_taylor_loss_grad.restype = C.c_double
@@ -143,8 +143,18 @@ def reference(m, Xref=None) -> Reference:
     return Reference(l0, th, A0, V0)
 
 
-def forces(m, X, ref: Reference, k=None, families=False):
-    """Returns dict(F, V, A, W[B,4], Ffam[4,N,3] if families)."""
+def _ew(m, ew):
+    """Per-edge weights [E][2] on (ks, kb) as float64, or None (all 1)."""
+    if ew is None:
+        return None
+    ew = _f64(np.asarray(ew).reshape(-1, 2))
+    assert ew.shape[0] == int(np.asarray(m.edge_off)[-1])
+    return ew
+
+
+def forces(m, X, ref: Reference, k=None, families=False, ew=None):
+    """Returns dict(F, V, A, W[B,4], Ffam[4,N,3] if families).  ew[E][2]:
+    per-edge weights on (ks, kb), None for all 1."""
     no, eo, fo, fa, e4 = _mesh_args(m)
     B = len(no) - 1
     N = int(no[-1])
@@ -160,7 +170,8 @@ def forces(m, X, ref: Reference, k=None, families=False):
                      _p(fa, C.c_int32), _p(e4, C.c_int32), _p(cl, C.c_uint8),
                      _p(X, C.c_double), _p(_f64(ref.l0), C.c_double),
                      _p(_f64(ref.theta0), C.c_double), _p(_f64(ref.A0), C.c_double),
-                     _p(_f64(ref.V0), C.c_double), _p(kk, C.c_double), _p(F, C.c_double),
+                     _p(_f64(ref.V0), C.c_double), _p(kk, C.c_double),
+                     _p(_ew(m, ew), C.c_double), _p(F, C.c_double),
                      _p(Ff, C.c_double), _p(V, C.c_double), _p(A, C.c_double),
                      _p(W, C.c_double))
     out = dict(F=F, V=V, A=A, W=W)
@@ -169,7 +180,7 @@ def forces(m, X, ref: Reference, k=None, families=False):
     return out
 
 
-def forces_jvp(m, X, dX, ref: Reference, k=None):
+def forces_jvp(m, X, dX, ref: Reference, k=None, ew=None):
     """(dF/dX) dX by the complex step; equal to the VJP (dF/dX symmetric)."""
     no, eo, fo, fa, e4 = _mesh_args(m)
     B = len(no) - 1
@@ -182,7 +193,7 @@ def forces_jvp(m, X, dX, ref: Reference, k=None):
                          _p(X, C.c_double), _p(dX, C.c_double), _p(_f64(ref.l0), C.c_double),
                          _p(_f64(ref.theta0), C.c_double), _p(_f64(ref.A0), C.c_double),
                          _p(_f64(ref.V0), C.c_double), _p(_k(m, k), C.c_double),
-                         _p(dF, C.c_double))
+                         _p(_ew(m, ew), C.c_double), _p(dF, C.c_double))
     return dF
 
 
@@ -223,7 +234,7 @@ def spread(X, Fn, grid, f=None):
     return f
 
 
-def step(m, X, ref: Reference, u, dt, f=None, k=None):
+def step(m, X, ref: Reference, u, dt, f=None, k=None, ew=None):
     """One explicit step; returns dict(X=new X, F, U, V, A, f)."""
     no, eo, fo, fa, e4 = _mesh_args(m)
     B = len(no) - 1
@@ -242,7 +253,8 @@ def step(m, X, ref: Reference, u, dt, f=None, k=None):
                    _p(pn, C.c_uint8), _p(ms, C.c_double), _p(Xn, C.c_double),
                    _p(_f64(ref.l0), C.c_double), _p(_f64(ref.theta0), C.c_double),
                    _p(_f64(ref.A0), C.c_double), _p(_f64(ref.V0), C.c_double),
-                   _p(_k(m, k), C.c_double), nx, ny, nz, h, _p(u, C.c_double),
+                   _p(_k(m, k), C.c_double), _p(_ew(m, ew), C.c_double), nx, ny, nz, h,
+                   _p(u, C.c_double),
                    _p(f, C.c_double), float(dt), _p(F, C.c_double), _p(U, C.c_double),
                    _p(V, C.c_double), _p(A, C.c_double))
     return dict(X=Xn, F=F, U=U, V=V, A=A, f=f)
@@ -275,7 +287,7 @@ def node_body(m):
     return np.repeat(np.arange(len(no) - 1), np.diff(no))
 
 
-def rollout_grad(m, X0, ref: Reference, u, dt, steps, Dstar, k=None):
+def rollout_grad(m, X0, ref: Reference, u, dt, steps, Dstar, k=None, ew=None):
     """Loss after ``steps`` explicit steps and its gradient by reverse mode.
 
     Forward: X^{n+1} = X^n + M (dt U(X^n) + dt^2/m F(X^n; k)), M = not pinned.
@@ -290,7 +302,7 @@ def rollout_grad(m, X0, ref: Reference, u, dt, steps, Dstar, k=None):
     c2 = (dt * dt / np.asarray(m.mass, np.float64))[nb][:, None]
     Xs = [_f64(X0).copy()]
     for _ in range(steps):
-        Xs.append(step(m, Xs[-1], ref, u, dt, None, kk)["X"])
+        Xs.append(step(m, Xs[-1], ref, u, dt, None, kk, ew)["X"])
     loss, lam = taylor_loss_grad(m, Xs[-1], Dstar)
     B = len(m.node_off) - 1
     gk = np.zeros((4, B))
@@ -302,8 +314,8 @@ def rollout_grad(m, X0, ref: Reference, u, dt, steps, Dstar, k=None):
         J = interp_jac(Xn, m.grid, u)
         # each family's force is linear in its own constant: dF_s/dk_s is the
         # family's force at unit constants (defined also where k_s = 0)
-        fu = forces(m, Xn, ref, np.ones_like(kk), families=True)
-        dF = forces_jvp(m, Xn, P, ref, kk)
+        fu = forces(m, Xn, ref, np.ones_like(kk), families=True, ew=ew)
+        dF = forces_jvp(m, Xn, P, ref, kk, ew)
         lam = lam + dt * np.einsum("lde,ld->le", J, P) + c2 * dF
         for s in range(4):
             contrib = (fu["Ffam"][s] * P).sum(axis=1) * c2[:, 0]

@@ -82,17 +82,19 @@ void orc_reference(int B, const int64_t *node_off, const int64_t *edge_off,
     r_reference(B, node_off, edge_off, face_off, faces, edges4, Xref, l0, theta0, A0, V0);
 }
 
-/* k = [4][B] (ks, kb, kA, kV).  Ffam, V, A, W may be NULL. */
+/* k = [4][B] (ks, kb, kA, kV); ew = [E][2] per-edge weights on ks and kb, or
+ * NULL (all 1).  Ffam, V, A, W may be NULL. */
 void orc_forces(int B, const int64_t *node_off, const int64_t *edge_off,
                 const int64_t *face_off, const int32_t *faces, const int32_t *edges4,
                 const uint8_t *closed, const double *X, const double *l0,
                 const double *theta0, const double *A0, const double *V0,
-                const double *k, double *F, double *Ffam, double *V, double *A, double *W)
+                const double *k, const double *ew, double *F, double *Ffam, double *V,
+                double *A, double *W)
 {
     double *Vt = V ? V : (double *)malloc(sizeof(double) * (B > 0 ? B : 1));
     double *At = A ? A : (double *)malloc(sizeof(double) * (B > 0 ? B : 1));
     r_forces(B, node_off, edge_off, face_off, faces, edges4, closed, X, l0, theta0, A0, V0,
-             k, k + B, k + 2 * B, k + 3 * B, F, Ffam, Vt, At, W);
+             k, k + B, k + 2 * B, k + 3 * B, ew, F, Ffam, Vt, At, W);
     if (!V) free(Vt);
     if (!A) free(At);
 }
@@ -103,7 +105,7 @@ void orc_forces_jvp(int B, const int64_t *node_off, const int64_t *edge_off,
                     const int64_t *face_off, const int32_t *faces, const int32_t *edges4,
                     const uint8_t *closed, const double *X, const double *dX,
                     const double *l0, const double *theta0, const double *A0,
-                    const double *V0, const double *k, double *dF)
+                    const double *V0, const double *k, const double *ew, double *dF)
 {
     int64_t N = node_off[B];
     double complex *Xc = malloc(sizeof(double complex) * 3 * N);
@@ -114,7 +116,7 @@ void orc_forces_jvp(int B, const int64_t *node_off, const int64_t *edge_off,
     for (int64_t i = 0; i < 3 * N; ++i) Xc[i] = X[i] + I * (CS_H * dX[i]);
     for (int64_t i = 0; i < 4 * B; ++i) kc[i] = k[i];
     c_forces(B, node_off, edge_off, face_off, faces, edges4, closed, Xc, l0, theta0, A0, V0,
-             kc, kc + B, kc + 2 * B, kc + 3 * B, Fc, NULL, Vc, Ac, NULL);
+             kc, kc + B, kc + 2 * B, kc + 3 * B, ew, Fc, NULL, Vc, Ac, NULL);
     for (int64_t i = 0; i < 3 * N; ++i) dF[i] = cimag(Fc[i]) / CS_H;
     free(Xc);
     free(Fc);
@@ -161,13 +163,13 @@ void orc_step(int B, const int64_t *node_off, const int64_t *edge_off,
               const int64_t *face_off, const int32_t *faces, const int32_t *edges4,
               const uint8_t *closed, const uint8_t *pinned, const double *mass,
               double *X, const double *l0, const double *theta0, const double *A0,
-              const double *V0, const double *k, int nx, int ny, int nz, double h,
-              const double *u, double *f, double dt, double *F, double *U, double *V,
-              double *A)
+              const double *V0, const double *k, const double *ew, int nx, int ny, int nz,
+              double h, const double *u, double *f, double dt, double *F, double *U,
+              double *V, double *A)
 {
     int64_t N = node_off[B];
     orc_forces(B, node_off, edge_off, face_off, faces, edges4, closed, X, l0, theta0, A0, V0,
-               k, F, NULL, V, A, NULL);
+               k, ew, F, NULL, V, A, NULL);
     r_interp(N, X, nx, ny, nz, h, u, U);
     if (f) r_spread(N, X, F, nx, ny, nz, h, f);
     for (int b = 0; b < B; ++b) {
