@@ -456,7 +456,7 @@ def main():
     launch = {"threads": plan.step_threads, "tile_bytes": plan.tile_bytes, "units": plan.n_units}
     traffic, traffic_src = load_traffic(wl.name, args.precision, launch)
     kernel = (f"k_step_fused<{'double' if args.precision == 'f64' else 'float'}, "
-              f"{plan.step_threads}>") if plan.fused else "unfused step"
+              f"{plan.step_threads}, false>") if plan.fused else "unfused step"
     if plan.patched_bodies:
         kernel += " + geometry and commit passes"
 

@@ -186,9 +186,24 @@ ip_status ip_reference_from(ip_plan *plan, const double *Xref, void *l0, void *c
  * (IP_ERR_OOM on failure); later calls allocate nothing. */
 ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *stream);
 
+/* Bind per-edge weights on the spring and bending constants (Section 2.3:
+ * on meshes of non-uniform triangles the edge stiffness varies edge by edge;
+ * the paper points to an external model for it and does not print the rule,
+ * so the weights come from the caller).  ew: device double[E][2], (w_s, w_b)
+ * for each edge in the mesh's edge order; edge e of body b then carries
+ * ks[b] w_s[e] and kb[b] w_b[e] in every later call on the plan (forces,
+ * energies, steps, their JVP and VJP; the constants' gradients are with
+ * respect to the per-body ks, kb with the weights held fixed).  NULL unbinds
+ * (every weight 1).  The weights are copied; the call synchronises `stream`
+ * and returns IP_ERR_ARG, leaving the previous weights unbound, if any weight
+ * is negative or not finite.  The first call allocates 16 bytes per edge and
+ * per edge record (IP_ERR_OOM on failure); later calls allocate nothing. */
+ip_status ip_plan_bind_edge_weights(ip_plan *plan, const double *ew, void *stream);
+
 /* Interaction-potential forces at positions X (Section 2.3):
- *   W_e = 1/2 ks (l - l0)^2               every edge
- *   W_b = kb (1 - cos(theta - theta0))    every edge with two faces
+ *   W_e = 1/2 ks w_s (l - l0)^2           every edge
+ *   W_b = kb w_b (1 - cos(theta - theta0)) every edge with two faces
+ * (w_s, w_b: the bound per-edge weights, 1 when none are bound)
  *   W_a = 1/2 kA ((A - A0)/A0)^2 A0       every triangle
  *   W_v = 1/2 kV ((V - V0)/V0)^2 V0       every closed body
  * F = -grad(sum W) -> F[N][3] (real, overwritten).  V[B], A[B] (double,

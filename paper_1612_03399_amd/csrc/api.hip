@@ -62,7 +62,7 @@ void free_plan(ip_plan *p) {
                     p->bref_A0, p->bref_V0, p->wu_body, p->wu_owned, p->wu_noff, p->wu_nodes,
                     p->wu_eoff, p->wu_foff, p->erec_perm, p->erec_lid, p->frec_perm,
                     p->frec_lid, p->edge_rec, p->face_rec, p->patched_bodies,
-                    p->patched_units, p->Xstage};
+                    p->patched_units, p->Xstage, p->ew_store, p->ew_rec_store, p->ew_bad};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete p;
@@ -409,6 +409,34 @@ ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *s
         IP_TRY(launch_pack_reference(plan, &plan->bref, s));
         plan->packed = 1;
     }
+    return IP_OK;
+}
+
+ip_status ip_plan_bind_edge_weights(ip_plan *plan, const double *ew, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (!ew) {
+        plan->ew = nullptr;
+        plan->ew_rec = nullptr;
+        return IP_OK;
+    }
+    if (!aligned(ew, 16)) return arg_error("misaligned weights");
+    if (!plan->ew_store) {
+        IP_TRY(alloc_bytes((void **)&plan->ew_store, (size_t)std::max<int64_t>(plan->E, 1) * 16));
+        IP_TRY(alloc_bytes((void **)&plan->ew_rec_store,
+                           (size_t)std::max<int64_t>(plan->n_erec, 1) * 16));
+        IP_TRY(upload(&plan->ew_bad, (const int32_t *)nullptr, 1));
+    }
+    // the weights are checked before they replace the bound ones
+    plan->ew = nullptr;
+    plan->ew_rec = nullptr;
+    IP_TRY(launch_bind_edge_weights(plan, ew, (hipStream_t)stream));
+    int32_t bad = 0;
+    IP_HIP_CHECK(hipMemcpyAsync(&bad, plan->ew_bad, sizeof(bad), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream));
+    IP_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    if (bad) return arg_error("edge weights must be finite and non-negative");
+    plan->ew = plan->ew_store;
+    plan->ew_rec = plan->n_erec > 0 ? plan->ew_rec_store : nullptr;
     return IP_OK;
 }
 

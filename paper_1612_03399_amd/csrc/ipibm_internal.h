@@ -102,6 +102,14 @@ struct ip_plan {
 
     double *bwd_dots = nullptr;   // [2E + 2F] family dot products (reverse step)
 
+    // per-edge weights on ks and kb (ip_plan_bind_edge_weights); NULL while
+    // none are bound (every weight 1)
+    double *ew = nullptr;         // [E][2] caller's edge order (element kernels)
+    double *ew_rec = nullptr;     // [n_erec][2] record order (fused kernels)
+    double *ew_store = nullptr;   // storage behind ew, kept across unbinding
+    double *ew_rec_store = nullptr;
+    int32_t *ew_bad = nullptr;    // device flag: an invalid weight was seen
+
     // bound reference (ip_plan_bind_reference): copies in the caller's
     // element order (element kernels; source of the packed records)
     bool ref_bound = false;
@@ -195,6 +203,7 @@ constexpr int kStepFacesPerThread = 8;   // faces held in registers per thread
 constexpr int kPatchOwned = 512;         // owned nodes per patch of a large body
 size_t step_fused_lds_bytes(int nmax, int tile_bytes);
 ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
+ip_status launch_bind_edge_weights(ip_plan *p, const double *ew, hipStream_t s);
 ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s);
 // owned nodes of patched units: src -> dst ([N][3] double each)
 ip_status launch_commit(ip_plan *p, const double *src, double *dst, hipStream_t s);

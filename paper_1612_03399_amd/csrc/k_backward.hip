@@ -65,10 +65,12 @@ __global__ __launch_bounds__(256) void k_edges_jvp(
     const double *__restrict__ X, const double *__restrict__ T, const int4 *__restrict__ e4,
     const int64_t *__restrict__ edge_off, int B, int64_t E, const double *__restrict__ l0,
     const double *__restrict__ cs0, const double *__restrict__ ks, const double *__restrict__ kb,
-    const double *__restrict__ P, double *__restrict__ slots, double *__restrict__ dotE) {
+    const double *__restrict__ ew, const double *__restrict__ P, double *__restrict__ slots,
+    double *__restrict__ dotE) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int b = body_of(edge_off, B, e);
+    const double ws = ew ? ew[2 * e] : 1.0, wb = ew ? ew[2 * e + 1] : 1.0;
     const int4 q = e4[e];
     const bool hinge = q.z >= 0 && q.w >= 0;
     const vec3<dual> x1 = ldXd(X, T, q.x), x2 = ldXd(X, T, q.y);
@@ -79,8 +81,8 @@ __global__ __launch_bounds__(256) void k_edges_jvp(
     }
     vec3<dual> fsp, h1, h2, h3, h4;
     edge_parts<dual, dual>(x1, x2, x3, x4, hinge, dual(l0[e]),
-                           dual(cs0[2 * e]), dual(cs0[2 * e + 1]), ks[b], kb[b], fsp, h1, h2, h3,
-                           h4);
+                           dual(cs0[2 * e]), dual(cs0[2 * e + 1]), ks[b] * ws, kb[b] * wb, fsp, h1,
+                           h2, h3, h4);
     const vec3<dual> f1 = fsp + h1, f2 = h2 - fsp;
     double *o = slots + 12 * e;
     o[0] = f1.x.d; o[1] = f1.y.d; o[2] = f1.z.d;
@@ -100,8 +102,8 @@ __global__ __launch_bounds__(256) void k_edges_jvp(
             const vec3<double> p3 = ldX(P, q.z), p4 = ldX(P, q.w);
             bend = dot(u1, p1) + dot(u2, p2) + dot(u3, p3) + dot(u4, p4);
         }
-        dotE[2 * e] = dot(u0, p1 - p2);
-        dotE[2 * e + 1] = bend;
+        dotE[2 * e] = ws * dot(u0, p1 - p2);
+        dotE[2 * e + 1] = wb * bend;
     }
 }
 
@@ -431,10 +433,12 @@ struct VjpArgs {
     const int32_t *wu_body, *wu_owned, *wu_nodes;
     const int64_t *wu_noff, *wu_eoff, *wu_foff;
     const void *erec, *frec;
+    const double *ew;             // [n_erec][2] per-edge weights on ks, kb (EW only)
     int unit_base, nmax, tile_bytes;
 };
 
-template <int NT>
+// EW: the edges carry per-edge weights on ks and kb (record order).
+template <int NT, bool EW>
 __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[4 * (NT / 64)];
@@ -572,20 +576,28 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
             vec3<dual> fsp, h1, h2, h3, h4;
             bad |= edge_parts<dual, dual>(x1, x2, x3, x4, hinge, dual(r.l0()), dual(r.c0()),
                                           dual(r.s0()), 1.0, 1.0, fsp, h1, h2, h3, h4);
-            addd(q.x, ks, fsp);
-            addd(q.y, -ks, fsp);
+            double ws = 1.0, wb = 1.0;
+            if constexpr (EW) {
+                const double2 wt = reinterpret_cast<const double2 *>(a.ew)[e0 + t];
+                ws = wt.x;
+                wb = wt.y;
+            }
+            const double kse = ks * ws, kbe = kb * wb;
+            addd(q.x, kse, fsp);
+            addd(q.y, -kse, fsp);
             if (hinge) {
-                addd(q.x, kb, h1);
-                addd(q.y, kb, h2);
-                addd(q.z, kb, h3);
-                addd(q.w, kb, h4);
+                addd(q.x, kbe, h1);
+                addd(q.y, kbe, h2);
+                addd(q.z, kbe, h3);
+                addd(q.w, kbe, h4);
             }
             if (whole || q.x < N) {
-                dot_s += fsp.x.v * (p1.x - p2.x) + fsp.y.v * (p1.y - p2.y) + fsp.z.v * (p1.z - p2.z);
+                dot_s += ws * (fsp.x.v * (p1.x - p2.x) + fsp.y.v * (p1.y - p2.y) +
+                               fsp.z.v * (p1.z - p2.z));
                 if (hinge)
-                    dot_b += h1.x.v * p1.x + h1.y.v * p1.y + h1.z.v * p1.z + h2.x.v * p2.x +
-                             h2.y.v * p2.y + h2.z.v * p2.z + h3.x.v * p3.x + h3.y.v * p3.y +
-                             h3.z.v * p3.z + h4.x.v * p4.x + h4.y.v * p4.y + h4.z.v * p4.z;
+                    dot_b += wb * (h1.x.v * p1.x + h1.y.v * p1.y + h1.z.v * p1.z + h2.x.v * p2.x +
+                                   h2.y.v * p2.y + h2.z.v * p2.z + h3.x.v * p3.x + h3.y.v * p3.y +
+                                   h3.z.v * p3.z + h4.x.v * p4.x + h4.y.v * p4.y + h4.z.v * p4.z);
             }
         }
     }
@@ -776,8 +788,8 @@ ip_status launch_forces_jvp(ip_plan *p, const double *X, const double *T, const 
     if (p->E > 0)
         hipLaunchKernelGGL(k_edges_jvp, dim3(nblocks(p->E, 256)), dim3(256), 0, s, X, T,
                            (const int4 *)p->edges4, p->edge_off, p->B, p->E,
-                           (const double *)ref->l0, (const double *)ref->cs0, k->ks, k->kb, P,
-                           slots, dotE);
+                           (const double *)ref->l0, (const double *)ref->cs0, k->ks, k->kb, p->ew,
+                           P, slots, dotE);
     if (p->F > 0)
         hipLaunchKernelGGL(k_faces_jvp, dim3(nblocks(p->F, 256)), dim3(256), 0, s, X, T, p->faces,
                            p->face_off, p->B, p->F, (const double *)ref->A0, ref->V0, V, dV,
@@ -832,9 +844,12 @@ ip_status prepare_step_vjp_fused(ip_plan *p) {
     for (int c = 0; c < p->n_step_classes; ++c) {
         const auto &sc = p->step_class[c];
         const int lds = (int)step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
-        const void *fn = sc.threads == 384 ? (const void *)k_step_vjp_fused<384>
-                                           : (const void *)k_step_vjp_fused<768>;
-        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        const void *fns[2] = {sc.threads == 384 ? (const void *)k_step_vjp_fused<384, false>
+                                                : (const void *)k_step_vjp_fused<768, false>,
+                              sc.threads == 384 ? (const void *)k_step_vjp_fused<384, true>
+                                                : (const void *)k_step_vjp_fused<768, true>};
+        for (const void *fn : fns)
+            IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     }
     return IP_OK;
 }
@@ -881,6 +896,7 @@ ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference 
     a.wu_foff = p->wu_foff;
     a.erec = p->edge_rec;
     a.frec = p->face_rec;
+    a.ew = p->ew_rec;
     if (p->n_patched_bodies > 0) {
         hipLaunchKernelGGL(k_volume_dual_masked, dim3(p->n_patched_bodies), dim3(256), 0, s, X,
                            lam_in, p->pinned, p->faces, p->node_off, p->face_off,
@@ -894,10 +910,17 @@ ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference 
         a.tile_bytes = sc.tile_bytes;
         const size_t lds = step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
         const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
-        if (sc.threads == 384)
-            hipLaunchKernelGGL(k_step_vjp_fused<384>, grid, block, lds, s, a);
-        else
-            hipLaunchKernelGGL(k_step_vjp_fused<768>, grid, block, lds, s, a);
+        if (sc.threads == 384) {
+            if (a.ew)
+                hipLaunchKernelGGL((k_step_vjp_fused<384, true>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((k_step_vjp_fused<384, false>), grid, block, lds, s, a);
+        } else {
+            if (a.ew)
+                hipLaunchKernelGGL((k_step_vjp_fused<768, true>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((k_step_vjp_fused<768, false>), grid, block, lds, s, a);
+        }
         IP_HIP_CHECK(hipGetLastError());
     }
     return launch_commit(p, p->Xstage, lam_out, s);

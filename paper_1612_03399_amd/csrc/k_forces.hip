@@ -92,10 +92,12 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
     const double *__restrict__ X, const int4 *__restrict__ e4,
     const int64_t *__restrict__ edge_off, int B, int64_t E, const R *__restrict__ l0,
     const R *__restrict__ cs0, const double *__restrict__ ks, const double *__restrict__ kb,
-    R *__restrict__ slots, uint32_t *__restrict__ status) {
+    const double *__restrict__ ew, R *__restrict__ slots, uint32_t *__restrict__ status) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int b = body_of(edge_off, B, e);
+    const double kse = ew ? ks[b] * ew[2 * e] : ks[b];
+    const double kbe = ew ? kb[b] * ew[2 * e + 1] : kb[b];
     const int4 q = e4[e];
     const vec3<double> x1 = ldX(X, q.x), x2 = ldX(X, q.y);
     vec3<double> x3, x4;
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
     }
     vec3<R> f1, f2, f3, f4;
     const bool bad = edge_forces<double, R>(x1, x2, x3, x4, hinge, l0[e],
-                                    cs0[2 * e], cs0[2 * e + 1], ks[b], kb[b], f1, f2, f3, f4);
+                                    cs0[2 * e], cs0[2 * e + 1], kse, kbe, f1, f2, f3, f4);
     if (bad) atomicOr(status, IP_STATUS_DEGENERATE);
     R *o = slots + 12 * e;
     o[0] = f1.x; o[1] = f1.y; o[2] = f1.z;
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_energy(
     const double *__restrict__ V0, const double *__restrict__ Vcur,
     const uint8_t *__restrict__ closed, const double *__restrict__ ks,
     const double *__restrict__ kb, const double *__restrict__ kA,
-    const double *__restrict__ kV, double *__restrict__ W) {
+    const double *__restrict__ kV, const double *__restrict__ ew, double *__restrict__ W) {
     __shared__ double sh[kGeomThreads / 64];
     const int b = blockIdx.x;
     double ws = 0.0, wb = 0.0, wa = 0.0;
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_energy(
         const vec3<double> x1 = ldX(X, q.x);
         const vec3<double> ev = ldX(X, q.y) - x1;
         const double dl = sqrt(dot(ev, ev)) - (double)l0[e];
-        ws += dl * dl;
+        ws += (ew ? ew[2 * e] : 1.0) * dl * dl;
         if (q.z >= 0 && q.w >= 0) {
             const vec3<double> nA = cross(ev, ldX(X, q.z) - x1);
             const vec3<double> nB = cross(ldX(X, q.w) - x1, ev);
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_energy(
             const double c0 = (double)cs0[2 * e], s0 = (double)cs0[2 * e + 1];
             const double r0 = 1.0 / sqrt(c0 * c0 + s0 * s0);
             const double cd = (cth * c0 + sth * s0) * r0, sd = (sth * c0 - cth * s0) * r0;
-            wb += cd > 0.0 ? sd * sd / (1.0 + cd) : 1.0 - cd;
+            wb += (ew ? ew[2 * e + 1] : 1.0) * (cd > 0.0 ? sd * sd / (1.0 + cd) : 1.0 - cd);
         }
     }
     for (int64_t f = face_off[b] + threadIdx.x; f < face_off[b + 1]; f += blockDim.x) {
@@ -240,7 +242,7 @@ ip_status forces_impl(ip_plan *p, const double *X, const ip_reference *ref,
     if (p->E > 0)
         hipLaunchKernelGGL(k_edges<R>, dim3(nblocks(p->E, kElemThreads)), dim3(kElemThreads), 0,
                            s, X, (const int4 *)p->edges4, p->edge_off, p->B, p->E,
-                           (const R *)ref->l0, (const R *)ref->cs0, k->ks, k->kb, slots,
+                           (const R *)ref->l0, (const R *)ref->cs0, k->ks, k->kb, p->ew, slots,
                            p->status);
     if (p->F > 0)
         hipLaunchKernelGGL(k_faces<R>, dim3(nblocks(p->F, kElemThreads)), dim3(kElemThreads), 0,
@@ -254,7 +256,7 @@ ip_status forces_impl(ip_plan *p, const double *X, const ip_reference *ref,
         hipLaunchKernelGGL(k_energy<R>, dim3(p->B), dim3(kGeomThreads), 0, s, X,
                            (const int4 *)p->edges4, p->faces, p->edge_off, p->face_off,
                            (const R *)ref->l0, (const R *)ref->cs0, (const R *)ref->A0, ref->V0,
-                           Vb, p->closed, k->ks, k->kb, k->kA, k->kV, W);
+                           Vb, p->closed, k->ks, k->kb, k->kA, k->kV, p->ew, W);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }
@@ -272,7 +274,43 @@ ip_status reference_impl(ip_plan *p, const double *X, void *l0, void *cs0, void 
     return IP_OK;
 }
 
+// Per-edge weights: checked (finite, non-negative), copied in the caller's
+// edge order and gathered into the record order of the fused kernels.
+__global__ void k_clear_flag(int32_t *flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
+__global__ __launch_bounds__(256) void k_copy_weights(const double *__restrict__ src, int64_t E,
+                                                      double *__restrict__ dst,
+                                                      int32_t *__restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * E) return;
+    const double w = src[i];
+    if (!(w >= 0.0) || !isfinite(w)) atomicOr(bad, 1);
+    dst[i] = w;
+}
+
+__global__ __launch_bounds__(256) void k_gather_weights(const double2 *__restrict__ ew,
+                                                        const int32_t *__restrict__ perm,
+                                                        int64_t n, double2 *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) out[r] = ew[perm[r]];
+}
+
 }  // namespace
+
+ip_status launch_bind_edge_weights(ip_plan *p, const double *ew, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, p->ew_bad);
+    if (p->E > 0)
+        hipLaunchKernelGGL(k_copy_weights, dim3(nblocks(2 * p->E, 256)), dim3(256), 0, s, ew,
+                           p->E, p->ew_store, p->ew_bad);
+    if (p->n_erec > 0)
+        hipLaunchKernelGGL(k_gather_weights, dim3(nblocks(p->n_erec, 256)), dim3(256), 0, s,
+                           (const double2 *)p->ew_store, p->erec_perm, p->n_erec,
+                           (double2 *)p->ew_rec_store);
+    IP_HIP_CHECK(hipGetLastError());
+    return IP_OK;
+}
 
 ip_status launch_geometry(ip_plan *p, const double *X, double *V, double *A, hipStream_t s,
                           const int32_t *bodies, int n_bodies) {

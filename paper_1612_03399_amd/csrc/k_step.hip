@@ -45,12 +45,14 @@ struct StepArgs {
     const int32_t *wu_body, *wu_owned, *wu_nodes;
     const int64_t *wu_noff, *wu_eoff, *wu_foff;
     const void *erec, *frec; // packed element records
+    const double *ew;        // [n_erec][2] per-edge weights on ks, kb (EW only)
     int unit_base;           // unit of workgroup 0 of this launch
     int nmax;                // node capacity of the LDS layout
     int tile_bytes;          // bytes of the tile region
 };
 
-template <typename R, int NT>
+// EW: the edges carry per-edge weights on ks and kb (record order).
+template <typename R, int NT, bool EW>
 __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[2 * (NT / 64)];
@@ -190,8 +192,14 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
             const int4 q = cur.ids();
             const bool hinge = q.z != kNoNode && q.w != kNoNode;
             vec3<R> f1, f2, f3, f4;
-            bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, cur.l0(), cur.c0(), cur.s0(), ks,
-                                          kb, f1, f2, f3, f4);
+            double kse = ks, kbe = kb;
+            if constexpr (EW) {
+                const double2 wt = reinterpret_cast<const double2 *>(a.ew)[e0 + t];
+                kse *= wt.x;
+                kbe *= wt.y;
+            }
+            bad |= edge_forces<double, R>(x1, x2, x3, x4, hinge, cur.l0(), cur.c0(), cur.s0(), kse,
+                                          kbe, f1, f2, f3, f4);
             if (t + NT < E) read_nodes(rc.ids(), x1, x2, x3, x4);
             add3(Fs, q.x, f1);
             add3(Fs, q.y, f2);
@@ -400,20 +408,33 @@ size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
     return (size_t)nmax * 48 + (size_t)tile_bytes + (size_t)nmax * 2 * sizeof(uint16_t);
 }
 
-template <typename R>
+template <typename R, bool EW>
 const void *step_kernel(int threads) {
-    return threads == 384 ? (const void *)k_step_fused<R, 384> : (const void *)k_step_fused<R, 768>;
+    return threads == 384 ? (const void *)k_step_fused<R, 384, EW>
+                          : (const void *)k_step_fused<R, 768, EW>;
 }
 
 ip_status prepare_step_fused(ip_plan *p) {
     for (int c = 0; c < p->n_step_classes; ++c) {
         const auto &sc = p->step_class[c];
         const int lds = (int)step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
-        const void *fn = p->prec == IP_F64 ? step_kernel<double>(sc.threads)
-                                           : step_kernel<float>(sc.threads);
-        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        const void *fns[2] = {
+            p->prec == IP_F64 ? step_kernel<double, false>(sc.threads)
+                              : step_kernel<float, false>(sc.threads),
+            p->prec == IP_F64 ? step_kernel<double, true>(sc.threads)
+                              : step_kernel<float, true>(sc.threads)};
+        for (const void *fn : fns)
+            IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     }
     return IP_OK;
+}
+
+template <typename R, int NT>
+void launch_step_variant(dim3 grid, dim3 block, size_t lds, hipStream_t s, const StepArgs &a) {
+    if (a.ew)
+        hipLaunchKernelGGL((k_step_fused<R, NT, true>), grid, block, lds, s, a);
+    else
+        hipLaunchKernelGGL((k_step_fused<R, NT, false>), grid, block, lds, s, a);
 }
 
 // The records must hold `ref` (packed by the caller of this launcher).
@@ -454,6 +475,7 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
     a.wu_foff = p->wu_foff;
     a.erec = p->edge_rec;
     a.frec = p->face_rec;
+    a.ew = p->ew_rec;
     // volume and area of patched bodies, before their patches need them
     if (p->n_patched_bodies > 0)
         IP_TRY(launch_geometry(p, X, a.V, a.A, s, p->patched_bodies, p->n_patched_bodies));
@@ -466,14 +488,14 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
         const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
         if (p->prec == IP_F64) {
             if (sc.threads == 384)
-                hipLaunchKernelGGL((k_step_fused<double, 384>), grid, block, lds, s, a);
+                launch_step_variant<double, 384>(grid, block, lds, s, a);
             else
-                hipLaunchKernelGGL((k_step_fused<double, 768>), grid, block, lds, s, a);
+                launch_step_variant<double, 768>(grid, block, lds, s, a);
         } else {
             if (sc.threads == 384)
-                hipLaunchKernelGGL((k_step_fused<float, 384>), grid, block, lds, s, a);
+                launch_step_variant<float, 384>(grid, block, lds, s, a);
             else
-                hipLaunchKernelGGL((k_step_fused<float, 768>), grid, block, lds, s, a);
+                launch_step_variant<float, 768>(grid, block, lds, s, a);
         }
         IP_HIP_CHECK(hipGetLastError());
     }

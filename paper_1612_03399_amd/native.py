@@ -78,6 +78,7 @@ def _load():
         "ip_plan_status": [vp, vp, C.POINTER(C.c_uint32)],
         "ip_forces_jvp": [vp, vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp],
         "ip_plan_bind_reference": [vp, C.POINTER(ip_reference), vp],
+        "ip_plan_bind_edge_weights": [vp, vp, vp],
         "ip_step_vjp": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, d, vp, vp,
                         vp, vp, vp],
         "ip_taylor": [vp, vp, vp, vp, vp, vp, vp],
@@ -349,6 +350,14 @@ def ip_taylor(plan: Plan, X, Dstar=None, stream=None):
     _check(LIB.ip_taylor(plan.handle, _ptr(X), _ptr(Dstar), _ptr(D), _ptr(loss), _ptr(gX),
                          _stream(stream)))
     return D, loss, gX
+
+
+def ip_plan_bind_edge_weights(plan: Plan, ew, stream=None):
+    """Bind per-edge weights ew[E][2] (float64 device tensor: w_s, w_b on the
+    body's ks, kb) for every later call on the plan; None unbinds."""
+    if ew is not None:
+        assert ew.dtype == torch.float64 and tuple(ew.shape) == (plan.E, 2) and ew.is_contiguous()
+    _check(LIB.ip_plan_bind_edge_weights(plan.handle, _ptr(ew), _stream(stream)))
 
 
 def ip_plan_bind_reference(plan: Plan, ref: Reference, stream=None):

@@ -1,0 +1,192 @@
+"""GPU parity of the per-edge weights on the spring and bending constants
+(ip_plan_bind_edge_weights) against the FP64 oracle, through the C-ABI: the
+forces and energies, the fused step (whole bodies and patches, both launch
+classes), the forces' JVP and the fused reverse step; unit weights give the
+unweighted bits, unbinding restores them, invalid weights are refused."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1612_03399_amd import native as N
+from paper_1612_03399_amd import workload as W
+
+from gpu_common import (DEV, TOL, constants, dev, elem_rel, gpu_reference_from_oracle, host,
+                        oracle_reference_as_seen, per_body_rel, rel_inf, step_error)
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "drop_L3_64": lambda: W.config0(),
+    "four_L4_128": lambda: W.small_suspension(4, 4, 128, r=0.04),
+    "uneven_small": lambda: W.config2(n_bodies=24, n=64),
+    "ventricle_small": lambda: W.config3(freq=12, leaflet_quads=10, noise_rel=0.2,
+                                         cells_per_unit=64),
+    "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
+                                           cells_per_unit=96),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def weights(wl, seed=17):
+    return np.random.default_rng(seed).uniform(0.25, 4.0, size=(wl.n_edges, 2))
+
+
+def kmat(wl):
+    return np.stack([wl.ks, wl.kb, wl.kA, wl.kV]).astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_weighted_forces_parity(case, precision):
+    say("weighted forces", case, precision)
+    wl = CASES[case]()
+    ref = O.reference(wl)
+    ew = weights(wl)
+    want = O.forces(wl, wl.X, oracle_reference_as_seen(ref, precision), ew=ew)
+    plan = N.Plan(wl, wl.grid, precision)
+    N.ip_plan_bind_edge_weights(plan, dev(ew))
+    Wt = torch.empty(wl.n_bodies, 4, dtype=torch.float64, device=DEV)
+    F = N.ip_forces(plan, dev(wl.X), gpu_reference_from_oracle(ref, precision), constants(wl),
+                    W=Wt)
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    e_f = per_body_rel(host(F).astype(np.float64), want["F"], wl.node_off)
+    e_w = elem_rel(host(Wt), want["W"])
+    say(f"  F {e_f:.2e}  W {e_w:.2e}")
+    assert e_f <= TOL[precision]
+    assert e_w <= (1e-10 if precision == "f64" else 1e-6)
+
+
+def weighted_step(wl, ref, precision, ew, options=None):
+    dt_ = N.real_dtype(precision)
+    u = wl.velocity()
+    if precision == "f32":
+        u = u.astype(np.float32).astype(np.float64)
+    plan = N.Plan(wl, wl.grid, precision, options)
+    N.ip_plan_bind_reference(plan, gpu_reference_from_oracle(ref, precision))
+    if ew is not None:
+        N.ip_plan_bind_edge_weights(plan, dev(ew))
+    X = dev(wl.X)
+    f = torch.zeros(u.shape, dtype=dt_, device=DEV)
+    N.ip_step(plan, X, None, constants(wl), dev(u, dt_), f, wl.dt)
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    return plan, u, host(X), host(f).astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_weighted_step_parity(case, precision):
+    """The fused step with bound weights against the oracle's weighted step
+    (patched shells and both launch classes included)."""
+    say("weighted step", case, precision)
+    wl = CASES[case]()
+    ref = O.reference(wl)
+    ew = weights(wl)
+    plan, u, Xg, fg = weighted_step(wl, ref, precision, ew)
+    assert plan.fused
+    f_want = np.zeros_like(u)
+    want = O.step(wl, wl.X, oracle_reference_as_seen(ref, precision), u, wl.dt, f_want, ew=ew)
+    e_x = step_error(wl, Xg, want["X"], wl.X, TOL[precision])
+    e_f = rel_inf(fg, f_want)
+    say(f"  X {e_x:.2f} of the bar  f {e_f:.2e}")
+    assert e_x <= 1.0 and e_f <= TOL[precision]
+    # the weights matter on this case: the unweighted step is far from it
+    plain = O.step(wl, wl.X, oracle_reference_as_seen(ref, precision), u, wl.dt, None)
+    assert step_error(wl, plain["X"], want["X"], wl.X, TOL[precision]) > 10.0
+
+
+@pytest.mark.parametrize("case", ["four_L4_128", "ventricle_patched"])
+def test_unit_weights_give_the_unweighted_bits(case):
+    """Weights of 1 multiply the constants exactly, so the weighted kernels
+    reproduce the unweighted step bit for bit; unbinding restores it too."""
+    say("unit weights", case)
+    wl = CASES[case]()
+    ref = O.reference(wl)
+    _, _, X0, f0 = weighted_step(wl, ref, "f64", None)
+    _, _, X1, f1 = weighted_step(wl, ref, "f64", np.ones((wl.n_edges, 2)))
+    assert np.array_equal(X0, X1)
+    # spreading adds with atomics: the field agrees to rounding, not bits
+    assert rel_inf(f1, f0) <= 1e-14
+    plan = N.Plan(wl, wl.grid, "f64")
+    gref = gpu_reference_from_oracle(ref, "f64")
+    Fa = host(N.ip_forces(plan, dev(wl.X), gref, constants(wl)))
+    N.ip_plan_bind_edge_weights(plan, dev(weights(wl)))
+    Fw = host(N.ip_forces(plan, dev(wl.X), gref, constants(wl)))
+    N.ip_plan_bind_edge_weights(plan, None)
+    Fb = host(N.ip_forces(plan, dev(wl.X), gref, constants(wl)))
+    assert np.array_equal(Fa, Fb) and not np.array_equal(Fa, Fw)
+
+
+@pytest.mark.parametrize("shape", [{"threads": 384}, {"unit_nodes": 768, "patch_owned": 256}])
+def test_weighted_step_launch_shapes(shape):
+    say("weighted step launch shape", shape)
+    wl = CASES["ventricle_patched"]()
+    ref = O.reference(wl)
+    ew = weights(wl, 5)
+    _, u, Xg, _ = weighted_step(wl, ref, "f64", ew, shape)
+    want = O.step(wl, wl.X, ref, u, wl.dt, None, ew=ew)
+    assert step_error(wl, Xg, want["X"], wl.X, TOL["f64"]) <= 1.0
+
+
+@pytest.mark.parametrize("case", ["four_L4_128", "ventricle_small", "ventricle_patched"])
+def test_weighted_jvp_and_step_vjp_parity(case):
+    """ip_forces_jvp and the fused reverse step with bound weights against the
+    oracle: lam = lam' + dt J_U^T P + dt^2/m dF(P), and the constants'
+    gradients from the weighted family forces at unit constants."""
+    say("weighted jvp / step_vjp", case)
+    wl = CASES[case]()
+    ref = O.reference(wl)
+    ew = weights(wl, 23)
+    plan = N.Plan(wl, wl.grid, "f64")
+    N.ip_plan_bind_edge_weights(plan, dev(ew))
+    gref = gpu_reference_from_oracle(ref, "f64")
+    k = constants(wl)
+    rng = np.random.default_rng(2)
+    dX = rng.normal(size=wl.X.shape) * 1e-2
+    got = host(N.ip_forces_jvp(plan, dev(wl.X), dev(dX), gref, k))
+    want = O.forces_jvp(wl, wl.X, dX, ref, kmat(wl), ew=ew)
+    e_j = per_body_rel(got, want, wl.node_off)
+
+    u = wl.velocity(dtype=np.float64)
+    dt = wl.dt
+    lam1 = rng.normal(size=wl.X.shape)
+    nb = O.node_body(wl)
+    mask = (1 - np.asarray(wl.pinned, np.float64))[:, None]
+    c2 = (dt * dt / np.asarray(wl.mass, np.float64))[nb][:, None]
+    P = mask * lam1
+    J = O.interp_jac(wl.X, wl.grid, u)
+    dF = O.forces_jvp(wl, wl.X, P, ref, kmat(wl), ew=ew)
+    want_lam = lam1 + dt * np.einsum("lde,ld->le", J, P) + c2 * dF
+    fu = O.forces(wl, wl.X, ref, np.ones((4, wl.n_bodies)), families=True, ew=ew)["Ffam"]
+    B = wl.n_bodies
+    want_gk = np.stack([np.bincount(nb, (fu[s] * P).sum(axis=1) * c2[:, 0], minlength=B)
+                        for s in range(4)])
+    gk = torch.zeros(4, B, dtype=torch.float64, device=DEV)
+    gu = torch.zeros(u.shape, dtype=torch.float64, device=DEV)
+    lam = N.ip_step_vjp(plan, dev(wl.X), gref, k, dev(u), dt, dev(lam1), gk=gk, gu=gu)
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    e_lam = per_body_rel(host(lam) - lam1, want_lam - lam1, wl.node_off)
+    e_gk = max(rel_inf(host(gk)[s], want_gk[s]) for s in range(4))
+    say(f"  jvp {e_j:.2e}  lam {e_lam:.2e}  gk {e_gk:.2e}")
+    assert e_j <= 1e-12 and e_lam <= 1e-12 and e_gk <= 1e-11
+
+
+def test_invalid_weights_are_refused():
+    wl = CASES["drop_L3_64"]()
+    ref = O.reference(wl)
+    plan = N.Plan(wl, wl.grid, "f64")
+    gref = gpu_reference_from_oracle(ref, "f64")
+    F0 = host(N.ip_forces(plan, dev(wl.X), gref, constants(wl)))
+    for bad in (-1.0, float("nan"), float("inf")):
+        ew = np.ones((wl.n_edges, 2))
+        ew[wl.n_edges // 2, 1] = bad
+        with pytest.raises(N.IpibmError):
+            N.ip_plan_bind_edge_weights(plan, dev(ew))
+    # a refused binding leaves the plan unweighted
+    assert np.array_equal(host(N.ip_forces(plan, dev(wl.X), gref, constants(wl))), F0)
