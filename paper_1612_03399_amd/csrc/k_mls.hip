@@ -14,6 +14,12 @@
 // Cholesky factor gives z = A^{-1} e_0 and phi_ijk = W_ijk (z0 + z1 dx_i +
 // z2 dy_j + z3 dz_k).  All MLS arithmetic is FP64; the fields are R.
 //
+// The per-axis parts are shared: along any axis the three MAC lattices sit at
+// only two offsets (integer or half cells), so a marker computes six axes for
+// all three lattices; the three weights of an axis take two exponentials
+// (w_{c-1,c+1} = w_c exp(-q^2) exp(+-2 d_c q^2)); and the Cholesky factor keeps
+// the reciprocals of its diagonal, so each solve is four divisions.
+//
 // Interpolation runs one thread per marker (its gathers of u hit in L2: the
 // faces of a body are consecutive).  Spreading on plans with work units runs
 // one workgroup per unit: the unit's positions go to LDS, each face whose
@@ -24,6 +30,7 @@
 // atomics 18.5 ms, the tiled form 0.8 ms; a tiled interpolation was slower
 // than the per-marker one, 0.69 against 0.61 ms.)
 #include <algorithm>
+#include <cmath>
 
 #include "step_common.h"
 
@@ -33,8 +40,117 @@ struct MlsGrid {
     int nx, ny, nz;
     double h, inv_h;
     int64_t plane, field;
+    // weight w(d) = exp(-(|d| q)^2), q = 1 / (1.5 alpha), d in cells
+    double inv_alpha;
+    double q2, cq;       // q^2 and exp(-q^2)
+    int fast;            // q^2 small enough for the two-exponential form
 };
 
+// One axis of a marker's MLS shape on lattices with a given offset along
+// that axis: the three support points c - 1, c, c + 1 around the marker.
+struct MlsAxis {
+    double w[3];         // weights
+    double dk[3];        // offsets (x^k - x) / h
+    int idx[3];          // wrapped lattice indices
+    int c;               // unwrapped index of the middle point
+    double s0, s1, s2;   // sum w, sum w d, sum w d^2
+};
+
+__device__ __forceinline__ void mls_axis(double xa, double off, int n, const MlsGrid &g,
+                                         MlsAxis &A) {
+    const double s = xa * g.inv_h - off;
+    double c = floor(s + 0.5);
+    if (!(fabs(c) < 1.0e9)) c = 0.0;           // non-finite or absurd position
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A.dk[j] = (c - 1.0 + j) - s;
+        A.idx[j] = wrapi((int)c - 1 + j, n);
+    }
+    A.c = (int)c;
+    const double r1 = fabs(A.dk[1]) * (1.0 / 1.5) * g.inv_alpha;
+    const double w1 = exp(-r1 * r1);
+    double w0, w2;
+    if (g.fast) {
+        // (d1 -+ 1)^2 q^2 = d1^2 q^2 -+ 2 d1 q^2 + q^2, so the outer weights
+        // are w1 exp(-q^2) exp(+-2 d1 q^2): two exponentials per axis
+        const double E = exp(2.0 * A.dk[1] * g.q2);
+        w0 = w1 * g.cq * E;
+        w2 = w1 * g.cq / E;
+    } else {
+        const double r0 = fabs(A.dk[0]) * (1.0 / 1.5) * g.inv_alpha;
+        const double r2 = fabs(A.dk[2]) * (1.0 / 1.5) * g.inv_alpha;
+        w0 = exp(-r0 * r0);
+        w2 = exp(-r2 * r2);
+    }
+    A.w[0] = fabs(A.dk[0]) <= 1.5 ? w0 : 0.0;
+    A.w[1] = fabs(A.dk[1]) <= 1.5 ? w1 : 0.0;
+    A.w[2] = fabs(A.dk[2]) <= 1.5 ? w2 : 0.0;
+    A.s0 = A.s1 = A.s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A.s0 += A.w[j];
+        A.s1 += A.w[j] * A.dk[j];
+        A.s2 += A.w[j] * A.dk[j] * A.dk[j];
+    }
+}
+
+// Both offsets of every axis for one marker: o0 (lattice points at integer
+// cells along the axis) and o5 (at half cells).  MAC lattice d is offset 0
+// along axis d and 1/2 along the others; the cell-centred lattice is 1/2
+// along all three.
+struct MlsAxes {
+    MlsAxis o0[3], o5[3];
+};
+
+__device__ __forceinline__ void mls_axes(const vec3<double> &x, const MlsGrid &g, MlsAxes &M) {
+    const double xs[3] = {x.x, x.y, x.z};
+    const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mls_axis(xs[a], 0.0, n[a], g, M.o0[a]);
+        mls_axis(xs[a], 0.5, n[a], g, M.o5[a]);
+    }
+}
+
+// Cholesky factor of the moment matrix A (symmetric, entries products of the
+// per-axis sums: A_00 = X0 Y0 Z0, A_01 = X1 Y0 Z0, ...) with the reciprocals
+// of its diagonal, and the solve of A x = b with it.
+struct MlsChol {
+    double l10, l20, l30, l21, l31, l32;
+    double r0, r1, r2, r3;   // 1 / l_ii
+};
+
+__device__ __forceinline__ void mls_factor(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
+                                           MlsChol &L) {
+    const double a00 = X.s0 * Y.s0 * Z.s0;
+    const double a01 = X.s1 * Y.s0 * Z.s0, a02 = X.s0 * Y.s1 * Z.s0, a03 = X.s0 * Y.s0 * Z.s1;
+    const double a11 = X.s2 * Y.s0 * Z.s0, a22 = X.s0 * Y.s2 * Z.s0, a33 = X.s0 * Y.s0 * Z.s2;
+    const double a12 = X.s1 * Y.s1 * Z.s0, a13 = X.s1 * Y.s0 * Z.s1, a23 = X.s0 * Y.s1 * Z.s1;
+    L.r0 = 1.0 / sqrt(a00);
+    L.l10 = a01 * L.r0;
+    L.l20 = a02 * L.r0;
+    L.l30 = a03 * L.r0;
+    L.r1 = 1.0 / sqrt(a11 - L.l10 * L.l10);
+    L.l21 = (a12 - L.l20 * L.l10) * L.r1;
+    L.l31 = (a13 - L.l30 * L.l10) * L.r1;
+    L.r2 = 1.0 / sqrt(a22 - L.l20 * L.l20 - L.l21 * L.l21);
+    L.l32 = (a23 - L.l30 * L.l20 - L.l31 * L.l21) * L.r2;
+    L.r3 = 1.0 / sqrt(a33 - L.l30 * L.l30 - L.l31 * L.l31 - L.l32 * L.l32);
+}
+
+__device__ __forceinline__ bool mls_solve(const MlsChol &L, const double b[4], double x[4]) {
+    const double y0 = b[0] * L.r0;
+    const double y1 = (b[1] - L.l10 * y0) * L.r1;
+    const double y2 = (b[2] - L.l20 * y0 - L.l21 * y1) * L.r2;
+    const double y3 = (b[3] - L.l30 * y0 - L.l31 * y1 - L.l32 * y2) * L.r3;
+    x[3] = y3 * L.r3;
+    x[2] = (y2 - L.l32 * x[3]) * L.r2;
+    x[1] = (y1 - L.l21 * x[2] - L.l31 * x[3]) * L.r1;
+    x[0] = (y0 - L.l10 * x[1] - L.l20 * x[2] - L.l30 * x[3]) * L.r0;
+    return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(x[3]);
+}
+
+// The shape of one marker on one lattice: per-axis parts and z = A^{-1} e_0.
 struct MlsShape {
     double w[3][3];      // per-axis weights of the 3 support points
     double dk[3][3];     // per-axis offsets (x^k - x) / h
@@ -43,54 +159,40 @@ struct MlsShape {
     int c[3];            // unwrapped index of the middle support point per axis
 };
 
-__device__ __forceinline__ bool mls_shape(const vec3<double> &x, int d, const MlsGrid &g,
-                                          double inv_alpha, MlsShape &S) {
-    const double xs[3] = {x.x, x.y, x.z};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    double s0[3], s1[3], s2[3];
+__device__ __forceinline__ bool mls_shape(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
+                                          MlsShape &S) {
+    const MlsAxis *ax[3] = {&X, &Y, &Z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double s = xs[a] * g.inv_h - mac_off(d, a);
-        double c = floor(s + 0.5);
-        if (!(fabs(c) < 1.0e9)) c = 0.0;           // non-finite or absurd position
-        s0[a] = s1[a] = s2[a] = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double dk = (c - 1.0 + j) - s;
-            const double r = fabs(dk) * (1.0 / 1.5) * inv_alpha;   // (r_k / alpha)
-            const double w = fabs(dk) <= 1.5 ? exp(-r * r) : 0.0;
-            S.w[a][j] = w;
-            S.dk[a][j] = dk;
-            S.idx[a][j] = wrapi((int)c - 1 + j, n[a]);
-            S.c[a] = (int)c;
-            s0[a] += w;
-            s1[a] += w * dk;
-            s2[a] += w * dk * dk;
+            S.w[a][j] = ax[a]->w[j];
+            S.dk[a][j] = ax[a]->dk[j];
+            S.idx[a][j] = ax[a]->idx[j];
         }
+        S.c[a] = ax[a]->c;
     }
-    // moment matrix (symmetric): A_00 = X0 Y0 Z0, A_01 = X1 Y0 Z0, ...
-    const double a00 = s0[0] * s0[1] * s0[2];
-    const double a01 = s1[0] * s0[1] * s0[2], a02 = s0[0] * s1[1] * s0[2], a03 = s0[0] * s0[1] * s1[2];
-    const double a11 = s2[0] * s0[1] * s0[2], a22 = s0[0] * s2[1] * s0[2], a33 = s0[0] * s0[1] * s2[2];
-    const double a12 = s1[0] * s1[1] * s0[2], a13 = s1[0] * s0[1] * s1[2], a23 = s0[0] * s1[1] * s1[2];
-    // Cholesky A = L L^T
-    const double l00 = sqrt(a00);
-    const double l10 = a01 / l00, l20 = a02 / l00, l30 = a03 / l00;
-    const double l11 = sqrt(a11 - l10 * l10);
-    const double l21 = (a12 - l20 * l10) / l11, l31 = (a13 - l30 * l10) / l11;
-    const double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
-    const double l32 = (a23 - l30 * l20 - l31 * l21) / l22;
-    const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32);
-    // L y = e_0, L^T z = y
-    const double y0 = 1.0 / l00;
-    const double y1 = -l10 * y0 / l11;
-    const double y2 = -(l20 * y0 + l21 * y1) / l22;
-    const double y3 = -(l30 * y0 + l31 * y1 + l32 * y2) / l33;
-    S.z[3] = y3 / l33;
-    S.z[2] = (y2 - l32 * S.z[3]) / l22;
-    S.z[1] = (y1 - l21 * S.z[2] - l31 * S.z[3]) / l11;
-    S.z[0] = (y0 - l10 * S.z[1] - l20 * S.z[2] - l30 * S.z[3]) / l00;
-    return isfinite(S.z[0]) && isfinite(S.z[1]) && isfinite(S.z[2]) && isfinite(S.z[3]);
+    MlsChol L;
+    mls_factor(X, Y, Z, L);
+    const double e0[4] = {1.0, 0.0, 0.0, 0.0};
+    return mls_solve(L, e0, S.z);
+}
+
+// Shape on MAC lattice d from a marker's shared axes (d a compile-time
+// constant after unrolling, so the axes stay in registers).
+__device__ __forceinline__ bool mls_shape(const MlsAxes &M, int d, MlsShape &S) {
+    return mls_shape(d == 0 ? M.o0[0] : M.o5[0], d == 1 ? M.o0[1] : M.o5[1],
+                     d == 2 ? M.o0[2] : M.o5[2], S);
+}
+
+// Shape on MAC lattice d at x, every axis computed here.
+__device__ __forceinline__ bool mls_shape(const vec3<double> &x, int d, const MlsGrid &g,
+                                          MlsShape &S) {
+    MlsAxis X, Y, Z;
+    mls_axis(x.x, mac_off(d, 0), g.nx, g, X);
+    mls_axis(x.y, mac_off(d, 1), g.ny, g, Y);
+    mls_axis(x.z, mac_off(d, 2), g.nz, g, Z);
+    return mls_shape(X, Y, Z, S);
 }
 
 __device__ __forceinline__ double mls_phi(const MlsShape &S, int i, int j, int k) {
@@ -114,17 +216,18 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_interp_mls(const double *__restrict__ X,
                                                     const int32_t *__restrict__ faces, int64_t F,
                                                     const R *__restrict__ u, MlsGrid g,
-                                                    double inv_alpha, R *__restrict__ U,
-                                                    uint32_t *status) {
+                                                    R *__restrict__ U, uint32_t *status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
+    MlsAxes M;
+    mls_axes(x, g, M);
     bool bad = false;
-#pragma unroll 1
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         MlsShape S;
-        bad |= !mls_shape(x, d, g, inv_alpha, S);
+        bad |= !mls_shape(M, d, S);
         const R *ud = u + d * g.field;
         double acc = 0.0;
 #pragma unroll
@@ -146,17 +249,18 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X,
                                                     const int32_t *__restrict__ faces, int64_t F,
                                                     const R *__restrict__ Fm, MlsGrid g,
-                                                    double inv_alpha, R *__restrict__ fld,
-                                                    uint32_t *status) {
+                                                    R *__restrict__ fld, uint32_t *status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
+    MlsAxes M;
+    mls_axes(x, g, M);
     bool bad = false;
-#pragma unroll 1
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         MlsShape S;
-        bad |= !mls_shape(x, d, g, inv_alpha, S);
+        bad |= !mls_shape(M, d, S);
         // sum_k phi_k (1 up to rounding, since A z = e_0), as the paper writes c_l
         double sphi = 0.0;
 #pragma unroll
@@ -187,17 +291,18 @@ __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X
 template <typename R>
 __global__ __launch_bounds__(256) void k_direct_forcing_mls(
     const double *__restrict__ X, const int32_t *__restrict__ faces, int64_t F,
-    const R *__restrict__ u, const R *__restrict__ Vb, MlsGrid g, double inv_alpha,
-    double inv_dt, R *__restrict__ Fout, R *__restrict__ fld, uint32_t *status) {
+    const R *__restrict__ u, const R *__restrict__ Vb, MlsGrid g, double inv_dt, R *__restrict__ Fout, R *__restrict__ fld, uint32_t *status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
+    MlsAxes M;
+    mls_axes(x, g, M);
     bool bad = false;
-#pragma unroll 1
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         MlsShape S;
-        bad |= !mls_shape(x, d, g, inv_alpha, S);
+        bad |= !mls_shape(M, d, S);
         const R *ud = u + d * g.field;
         double U = 0.0, sphi = 0.0;
 #pragma unroll
@@ -229,72 +334,32 @@ __global__ __launch_bounds__(256) void k_direct_forcing_mls(
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
 
-// MLS fit about y on a lattice with offsets off (cells): a = A^{-1} B q, the
-// linear fit q ~ a0 + a1 dx + a2 dy + a3 dz (offsets in units of h); a0 is
-// the MLS value at y and a1..a3 / h its gradient.  Returns false if the
-// solve is not finite.
+// MLS fit about a point on one lattice, from its per-axis shape parts:
+// a = A^{-1} B q, the linear fit q ~ a0 + a1 dx + a2 dy + a3 dz (offsets in
+// units of h); a0 is the MLS value at the point and a1..a3 / h its gradient.
+// Returns false if the solve is not finite.
 template <typename R>
-__device__ __forceinline__ bool mls_fit(const vec3<double> &y, const double off[3], const MlsGrid &g,
-                                        double inv_alpha, const R *__restrict__ q, double a[4]) {
-    const double ys[3] = {y.x, y.y, y.z};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    double w[3][3], dk[3][3], s0[3], s1[3], s2[3];
-    int idx[3][3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const double s = ys[ax] * g.inv_h - off[ax];
-        double c = floor(s + 0.5);
-        if (!(fabs(c) < 1.0e9)) c = 0.0;
-        s0[ax] = s1[ax] = s2[ax] = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double d = (c - 1.0 + j) - s;
-            const double r = fabs(d) * (1.0 / 1.5) * inv_alpha;
-            const double wj = fabs(d) <= 1.5 ? exp(-r * r) : 0.0;
-            w[ax][j] = wj;
-            dk[ax][j] = d;
-            idx[ax][j] = wrapi((int)c - 1 + j, n[ax]);
-            s0[ax] += wj;
-            s1[ax] += wj * d;
-            s2[ax] += wj * d * d;
-        }
-    }
+__device__ __forceinline__ bool mls_fit(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
+                                        const MlsGrid &g, const R *__restrict__ q, double a[4]) {
     // B q: weighted moments of the 27 values
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const R *row = q + (int64_t)idx[2][k] * g.plane + (int64_t)idx[1][j] * g.nx;
+            const R *row = q + (int64_t)Z.idx[k] * g.plane + (int64_t)Y.idx[j] * g.nx;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double wq = w[0][i] * w[1][j] * w[2][k] * (double)row[idx[0][i]];
-                m0 += wq;
-                m1 += wq * dk[0][i];
-                m2 += wq * dk[1][j];
-                m3 += wq * dk[2][k];
+                const double wq = X.w[i] * Y.w[j] * Z.w[k] * (double)row[X.idx[i]];
+                m[0] += wq;
+                m[1] += wq * X.dk[i];
+                m[2] += wq * Y.dk[j];
+                m[3] += wq * Z.dk[k];
             }
         }
-    const double a00 = s0[0] * s0[1] * s0[2];
-    const double a01 = s1[0] * s0[1] * s0[2], a02 = s0[0] * s1[1] * s0[2], a03 = s0[0] * s0[1] * s1[2];
-    const double a11 = s2[0] * s0[1] * s0[2], a22 = s0[0] * s2[1] * s0[2], a33 = s0[0] * s0[1] * s2[2];
-    const double a12 = s1[0] * s1[1] * s0[2], a13 = s1[0] * s0[1] * s1[2], a23 = s0[0] * s1[1] * s1[2];
-    const double l00 = sqrt(a00);
-    const double l10 = a01 / l00, l20 = a02 / l00, l30 = a03 / l00;
-    const double l11 = sqrt(a11 - l10 * l10);
-    const double l21 = (a12 - l20 * l10) / l11, l31 = (a13 - l30 * l10) / l11;
-    const double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
-    const double l32 = (a23 - l30 * l20 - l31 * l21) / l22;
-    const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32);
-    const double y0 = m0 / l00;
-    const double y1 = (m1 - l10 * y0) / l11;
-    const double y2 = (m2 - l20 * y0 - l21 * y1) / l22;
-    const double y3 = (m3 - l30 * y0 - l31 * y1 - l32 * y2) / l33;
-    a[3] = y3 / l33;
-    a[2] = (y2 - l32 * a[3]) / l22;
-    a[1] = (y1 - l21 * a[2] - l31 * a[3]) / l11;
-    a[0] = (y0 - l10 * a[1] - l20 * a[2] - l30 * a[3]) / l00;
-    return isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]) && isfinite(a[3]);
+    MlsChol L;
+    mls_factor(X, Y, Z, L);
+    return mls_solve(L, m, a);
 }
 
 // External loads on face f from probes of length h along its unit normal:
@@ -307,7 +372,7 @@ __global__ __launch_bounds__(256) void k_probe_loads(
     const double *__restrict__ X, const int32_t *__restrict__ faces,
     const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
     const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
-    double inv_alpha, double mu, R *__restrict__ Fext, uint32_t *status) {
+    double mu, R *__restrict__ Fext, uint32_t *status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     // body of face f: the last b with face_off[b] <= f
@@ -330,7 +395,6 @@ __global__ __launch_bounds__(256) void k_probe_loads(
     const double an = acc == nullptr ? 0.0
                                      : (double)acc[3 * f] * nu.x + (double)acc[3 * f + 1] * nu.y +
                                            (double)acc[3 * f + 2] * nu.z;
-    const double cc_off[3] = {0.5, 0.5, 0.5};
     const int sides = closed[lo] ? 1 : 2;
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
     bool bad = !(nlen > 0.0);
@@ -338,13 +402,24 @@ __global__ __launch_bounds__(256) void k_probe_loads(
     for (int side = 0; side < sides; ++side) {
         const double sg = side == 0 ? 1.0 : -1.0;
         const vec3<double> y{xc.x + sg * g.h * nu.x, xc.y + sg * g.h * nu.y, xc.z + sg * g.h * nu.z};
+        // the pressure lattice (cell centres) takes the half-cell axes on
+        // all three axes; velocity lattice i the integer one along axis i
         double ap[4], G[3][3];
-        bad |= !mls_fit<R>(y, cc_off, g, inv_alpha, pr, ap);
+        {
+            MlsAxis X, Y, Z;
+            mls_axis(y.x, 0.5, g.nx, g, X);
+            mls_axis(y.y, 0.5, g.ny, g, Y);
+            mls_axis(y.z, 0.5, g.nz, g, Z);
+            bad |= !mls_fit<R>(X, Y, Z, g, pr, ap);
+        }
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {
-            const double off[3] = {mac_off(i, 0), mac_off(i, 1), mac_off(i, 2)};
             double ai[4];
-            bad |= !mls_fit<R>(y, off, g, inv_alpha, u + i * g.field, ai);
+            MlsAxis X, Y, Z;
+            mls_axis(y.x, mac_off(i, 0), g.nx, g, X);
+            mls_axis(y.y, mac_off(i, 1), g.ny, g, Y);
+            mls_axis(y.z, mac_off(i, 2), g.nz, g, Z);
+            bad |= !mls_fit<R>(X, Y, Z, g, u + i * g.field, ai);
             G[i][0] = ai[1] * g.inv_h;
             G[i][1] = ai[2] * g.inv_h;
             G[i][2] = ai[3] * g.inv_h;
@@ -392,7 +467,6 @@ struct MlsUnitArgs {
     double inv_dt;
     void *f;
     MlsGrid g;
-    double inv_alpha;
     uint32_t *status;
     const int64_t *node_off;
     const int32_t *wu_body, *wu_owned, *wu_nodes, *frec_perm;
@@ -486,7 +560,7 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
             const double area = 0.5 * sqrt(dot(n, n));
             const vec3<double> p = marker_of(xs, q);
             MlsShape S;
-            bad |= !mls_shape(p, d, g, a.inv_alpha, S);
+            bad |= !mls_shape(p, d, g, S);
             double sphi = 0.0;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -579,7 +653,7 @@ __global__ __launch_bounds__(256) void k_centroid_to_nodes(const int32_t *__rest
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-MlsGrid mls_grid(const ip_plan *p) {
+MlsGrid mls_grid(const ip_plan *p, double alpha) {
     MlsGrid g;
     g.nx = p->grid.nx;
     g.ny = p->grid.ny;
@@ -588,6 +662,14 @@ MlsGrid mls_grid(const ip_plan *p) {
     g.inv_h = 1.0 / p->grid.h;
     g.plane = (int64_t)g.nx * g.ny;
     g.field = g.plane * g.nz;
+    g.inv_alpha = 1.0 / alpha;
+    const double q = (1.0 / 1.5) * g.inv_alpha;
+    g.q2 = q * q;
+    g.cq = std::exp(-g.q2);
+    // with q^2 <= 200 the factors exp(+-2 d q^2), |d| <= 1/2, and exp(-q^2)
+    // stay far inside the double range; beyond, each weight takes its own
+    // exponential
+    g.fast = g.q2 <= 200.0 ? 1 : 0;
     return g;
 }
 
@@ -601,8 +683,7 @@ static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArg
     IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                        p->device));
     a.X = X;
-    a.g = mls_grid(p);
-    a.inv_alpha = 1.0 / alpha;
+    a.g = mls_grid(p, alpha);
     a.status = p->status;
     a.node_off = p->node_off;
     a.wu_body = p->wu_body;
@@ -623,14 +704,14 @@ constexpr int kMlsThreads = 512;
 ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double alpha, void *U,
                             hipStream_t s) {
     if (p->F == 0) return IP_OK;
-    const MlsGrid g = mls_grid(p);
+    const MlsGrid g = mls_grid(p, alpha);
     const dim3 grid(nblocks(p->F, 256)), block(256);
     if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_interp_mls<double>, grid, block, 0, s, X, p->faces, p->F,
-                           (const double *)u, g, 1.0 / alpha, (double *)U, p->status);
+                           (const double *)u, g, (double *)U, p->status);
     else
         hipLaunchKernelGGL(k_interp_mls<float>, grid, block, 0, s, X, p->faces, p->F,
-                           (const float *)u, g, 1.0 / alpha, (float *)U, p->status);
+                           (const float *)u, g, (float *)U, p->status);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }
@@ -638,7 +719,7 @@ ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double a
 ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double alpha, void *f,
                             hipStream_t s) {
     if (p->F == 0) return IP_OK;
-    const MlsGrid g = mls_grid(p);
+    const MlsGrid g = mls_grid(p, alpha);
     if (p->fused_all && p->n_units > 0) {
         MlsUnitArgs a{};
         size_t lds = 0;
@@ -660,10 +741,10 @@ ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double 
     const dim3 grid(nblocks(p->F, 256)), block(256);
     if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_spread_mls<double>, grid, block, 0, s, X, p->faces, p->F,
-                           (const double *)Fm, g, 1.0 / alpha, (double *)f, p->status);
+                           (const double *)Fm, g, (double *)f, p->status);
     else
         hipLaunchKernelGGL(k_spread_mls<float>, grid, block, 0, s, X, p->faces, p->F,
-                           (const float *)Fm, g, 1.0 / alpha, (float *)f, p->status);
+                           (const float *)Fm, g, (float *)f, p->status);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }
@@ -671,7 +752,7 @@ ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double 
 ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb, const void *u,
                                     double alpha, double dt, void *Fout, void *f, hipStream_t s) {
     if (p->F == 0) return IP_OK;
-    const MlsGrid g = mls_grid(p);
+    const MlsGrid g = mls_grid(p, alpha);
     if (p->fused_all && p->n_units > 0) {
         MlsUnitArgs a{};
         size_t lds = 0;
@@ -696,11 +777,11 @@ ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb,
     const dim3 grid(nblocks(p->F, 256)), block(256);
     if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_direct_forcing_mls<double>, grid, block, 0, s, X, p->faces, p->F,
-                           (const double *)u, (const double *)Vb, g, 1.0 / alpha, 1.0 / dt,
+                           (const double *)u, (const double *)Vb, g, 1.0 / dt,
                            (double *)Fout, (double *)f, p->status);
     else
         hipLaunchKernelGGL(k_direct_forcing_mls<float>, grid, block, 0, s, X, p->faces, p->F,
-                           (const float *)u, (const float *)Vb, g, 1.0 / alpha, 1.0 / dt,
+                           (const float *)u, (const float *)Vb, g, 1.0 / dt,
                            (float *)Fout, (float *)f, p->status);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
@@ -709,16 +790,16 @@ ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb,
 ip_status launch_probe_loads(ip_plan *p, const double *X, const void *u, const void *pr,
                              const void *acc, double alpha, double mu, void *Fext, hipStream_t s) {
     if (p->F == 0) return IP_OK;
-    const MlsGrid g = mls_grid(p);
+    const MlsGrid g = mls_grid(p, alpha);
     const dim3 grid(nblocks(p->F, 256)), block(256);
     if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_probe_loads<double>, grid, block, 0, s, X, p->faces, p->face_off,
                            p->closed, p->B, p->F, (const double *)u, (const double *)pr,
-                           (const double *)acc, g, 1.0 / alpha, mu, (double *)Fext, p->status);
+                           (const double *)acc, g, mu, (double *)Fext, p->status);
     else
         hipLaunchKernelGGL(k_probe_loads<float>, grid, block, 0, s, X, p->faces, p->face_off,
                            p->closed, p->B, p->F, (const float *)u, (const float *)pr,
-                           (const float *)acc, g, 1.0 / alpha, mu, (float *)Fext, p->status);
+                           (const float *)acc, g, mu, (float *)Fext, p->status);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }
