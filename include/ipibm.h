@@ -277,7 +277,9 @@ ip_status ibm_direct_forcing_mls(ip_plan *plan, const double *X, const void *Vb,
  * gradient is that of the local MLS linear fit; the acceleration correction
  * carries the probe's side s.  u: real[3][nz][ny][nx]; p: real[nz][ny][nx];
  * acc: real[F][3] marker acceleration Du/Dt (may be NULL: zero); Fext:
- * real[F][3] (overwritten).  alpha positive, mu >= 0, both finite. */
+ * real[F][3] (overwritten).  alpha positive, mu >= 0, both finite.  A
+ * zero-area face has no normal: its load is 0 and IP_STATUS_DEGENERATE is
+ * set (IP_STATUS_NONFINITE for a non-finite normal). */
 ip_status ibm_probe_loads(ip_plan *plan, const double *X, const void *u, const void *p,
                           const void *acc, double alpha, double mu, void *Fext, void *stream);
 

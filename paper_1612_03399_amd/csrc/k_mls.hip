@@ -388,6 +388,14 @@ __global__ __launch_bounds__(256) void k_probe_loads(
                        xc3 = ldX(X, faces[3 * f + 2]);
     const vec3<double> nn = cross(xb - xa, xc3 - xa);
     const double nlen = sqrt(dot(nn, nn));
+    if (!(nlen > 0.0)) {
+        // a zero-area face has no normal: no probe, no load
+        Fext[3 * f] = (R)0.0;
+        Fext[3 * f + 1] = (R)0.0;
+        Fext[3 * f + 2] = (R)0.0;
+        atomicOr(status, nlen == 0.0 ? IP_STATUS_DEGENERATE : IP_STATUS_NONFINITE);
+        return;
+    }
     const double area = 0.5 * nlen;
     const vec3<double> nu{nn.x / nlen, nn.y / nlen, nn.z / nlen};
     const vec3<double> xc{(xa.x + xb.x + xc3.x) * (1.0 / 3.0), (xa.y + xb.y + xc3.y) * (1.0 / 3.0),
@@ -397,7 +405,7 @@ __global__ __launch_bounds__(256) void k_probe_loads(
                                            (double)acc[3 * f + 2] * nu.z;
     const int sides = closed[lo] ? 1 : 2;
     double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-    bool bad = !(nlen > 0.0);
+    bool bad = false;
 #pragma unroll 1
     for (int side = 0; side < sides; ++side) {
         const double sg = side == 0 ? 1.0 : -1.0;

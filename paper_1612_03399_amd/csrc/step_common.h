@@ -313,7 +313,7 @@ struct BlockDims {
 template <typename R, int D>
 __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, int p0, int p1,
                                             const int kc[3], const int kmin[3], int Tx, int Ty,
-                                            int T, double inv_h, double inv_h3, double *tile,
+                                            int Tz, double inv_h, double inv_h3, double *tile,
                                             bool &bad) {
     using Dm = BlockDims<D>;
     R acc[Dm::LZ][Dm::LY][Dm::LX];
@@ -323,6 +323,10 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
         for (int y = 0; y < Dm::LY; ++y)
 #pragma unroll
             for (int x = 0; x < Dm::LX; ++x) acc[z][y][x] = 0;
+    // the block's first and last planes along the lattice's unstaggered axis
+    // carry weight only from nodes whose stencil centre is the cell (first)
+    // or the next one (last)
+    bool used0 = false, used3 = false;
     for (int p = p0; p < p1; ++p) {
         R wx[4], wy[4], wz[4];
 #pragma unroll
@@ -337,6 +341,8 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
                 w[1] = s1 ? w3[0] : w3[1];
                 w[2] = s1 ? w3[1] : w3[2];
                 w[3] = s1 ? w3[2] : (R)0;
+                used0 |= !s1;
+                used3 |= s1;
                 if (sh != 0 && sh != 1) bad = true;
             } else {
                 w[0] = w3[0];
@@ -357,17 +363,31 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
             }
         }
     }
-    // block origin in tile coordinates: point k - 1 is tile index k - kmin
+    // block origin in tile coordinates: point k - 1 is tile index k - kmin.
+    // The tile spans the cells' box with one point below and two above, so
+    // the block lies inside it; one check for the whole block.
     const int ox = kc[0] - kmin[0], oy = kc[1] - kmin[1], oz = kc[2] - kmin[2];
+    if (!(ox >= 0 && oy >= 0 && oz >= 0 && ox + Dm::LX <= Tx && oy + Dm::LY <= Ty &&
+          oz + Dm::LZ <= Tz)) {
+        bad = true;
+        return;
+    }
+    double *base = tile + (oz * Ty + oy) * Tx + ox;
+    const int sz = Tx * Ty;
+    // plane by plane along the unstaggered axis, so that the optional first
+    // and last planes are one branch each
 #pragma unroll
-    for (int z = 0; z < Dm::LZ; ++z)
+    for (int q = 0; q < 4; ++q) {
+        if ((q == 0 && !used0) || (q == 3 && !used3)) continue;
 #pragma unroll
-        for (int y = 0; y < Dm::LY; ++y)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int x = 0; x < Dm::LX; ++x) {
-                const int t = ((oz + z) * Ty + (oy + y)) * Tx + (ox + x);
-                if (acc[z][y][x] != (R)0 && t >= 0 && t < T) lds_add(tile + t, (double)acc[z][y][x]);
+            for (int b = 0; b < 3; ++b) {
+                const int x = D == 0 ? q : a, y = D == 1 ? q : (D == 0 ? a : b),
+                          z = D == 2 ? q : b;
+                lds_add(base + z * sz + y * Tx + x, (double)acc[z][y][x]);
             }
+    }
 }
 
 // Raw packed records (vector loads) and their fields.
@@ -612,13 +632,13 @@ __device__ void spread_to_grid(const double *xs, const double *vals, int N, cons
                 const int kcell[3] = {cell_of(xs[3 * p], inv_h), cell_of(xs[3 * p + 1], inv_h),
                                       cell_of(xs[3 * p + 2], inv_h)};
                 if (d == 0)
-                    spread_cell<R, 0>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.T, inv_h,
+                    spread_cell<R, 0>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.Tz, inv_h,
                                       inv_h3, ftile, bad);
                 else if (d == 1)
-                    spread_cell<R, 1>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.T, inv_h,
+                    spread_cell<R, 1>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.Tz, inv_h,
                                       inv_h3, ftile, bad);
                 else
-                    spread_cell<R, 2>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.T, inv_h,
+                    spread_cell<R, 2>(xs, vals, p, q, kcell, tg.kmin, tg.Tx, tg.Ty, tg.Tz, inv_h,
                                       inv_h3, ftile, bad);
             }
             lds_barrier();

@@ -231,3 +231,38 @@ def test_probe_loads_rejects_bad_arguments():
     for alpha, mu in ((0.0, 0.1), (float("nan"), 0.1), (0.4, -1.0), (0.4, float("inf"))):
         with pytest.raises(N.IpibmError):
             N.ibm_probe_loads(plan, X, u, p, alpha, mu)
+
+
+def test_probe_loads_degenerate_face_and_empty_batch():
+    """A collapsed face gets no load and sets the degenerate flag, the other
+    faces match the oracle; an empty batch is a no-op."""
+    wl = CASES["drop_L3_64"]()
+    X = wl.X.copy()
+    a, b, c = wl.faces[11]
+    X[c] = X[a]
+    u, p, acc = probe_inputs(wl, "f64")
+    plan = N.Plan(wl, wl.grid, "f64")
+    got = host(N.ibm_probe_loads(plan, dev(X), dev(u), dev(p), 0.4, 0.02, acc=dev(acc)))
+    code, flags = N.ip_plan_status(plan)
+    assert flags & N.IP_STATUS_DEGENERATE and not flags & N.IP_STATUS_NONFINITE
+    fa = np.asarray(wl.faces)
+    area = 0.5 * np.linalg.norm(np.cross(X[fa[:, 1]] - X[fa[:, 0]], X[fa[:, 2]] - X[fa[:, 0]]),
+                                axis=1)
+    dead = area == 0.0
+    # the collapsed face has an exactly zero edge vector, so no normal; its
+    # neighbour across the collapsed edge has two equal edge vectors, whose
+    # cross product with fused multiply-adds is a rounding residue rather
+    # than zero: a vanishing area and load
+    assert dead.sum() == 2 and dead[11]
+    assert np.array_equal(got[11], np.zeros(3))
+    assert np.abs(got[dead]).max() <= 1e-12 * np.abs(got[~dead]).max()
+    keep = np.flatnonzero(~dead)
+    sub = types.SimpleNamespace(faces=fa[keep], closed=[1], face_off=[0, keep.size])
+    want = O.probe_loads(sub, X, wl.grid, u, p, 0.4, 0.02, acc=acc[keep])
+    assert rel_inf(got[keep], want) <= TOL["f64"]
+    empty = W._assemble([], "empty", wl.grid, 1e-4, 1, "f64", (1.0, 1.0, 1.0, 1.0))
+    plan = N.Plan(empty, empty.grid, "f64")
+    z = torch.zeros(0, 3, dtype=torch.float64, device=DEV)
+    out = N.ibm_probe_loads(plan, z, dev(u), dev(p), 0.4, 0.02)
+    assert out.shape == (0, 3)
+    assert N.ip_plan_status(plan)[0] == N.IP_OK
