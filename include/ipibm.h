@@ -329,6 +329,20 @@ ip_status ip_step_vjp(ip_plan *plan, const double *X, const ip_reference *ref,
                       const ip_constants *k, const double *u, double dt, const double *lam_next,
                       double *lam, double *gk, double *gu, void *stream);
 
+/* Adjoint of the interpolation ibm_interp (Section 2.2 transfer; the
+ * backward pass of the calibration workload): for a cotangent dU[N][3] on the
+ * interpolated velocities U = I(X) u,
+ *   gX[l] = sum_d dU[l][d] dU_d/dX_l  (J_U^T dU: the 3-point delta and its
+ *           derivative per axis; overwritten; may be NULL),
+ *   gu_d[k] += sum_l dU[l][d] w_k(X_l)  (the transpose of interpolation,
+ *           i.e. spreading without the 1/h^3; accumulated, the caller zeroes
+ *           it; may be NULL).
+ * X, dU, gX: double[N][3]; u, gu: double[3][nz][ny][nx].  IP_F64 plans only
+ * (IP_ERR_UNSUPPORTED otherwise); gu is summed with device atomics, so it is
+ * reproducible to rounding, not bitwise. */
+ip_status ibm_interp_vjp(ip_plan *plan, const double *X, const double *u, const double *dU,
+                         double *gX, double *gu, void *stream);
+
 /* Taylor deformation of every body (Section 3.1 measure D = (L - B)/(L + B)):
  * L^2 and B^2 are the largest and smallest eigenvalues of the node covariance
  * C = (1/n) sum (x - c)(x - c)^T (our reading of the semi-axes).  D[B] may be

@@ -592,6 +592,18 @@ ip_status ip_step_vjp(ip_plan *plan, const double *X, const ip_reference *ref,
                            (double *)gu, s);
 }
 
+ip_status ibm_interp_vjp(ip_plan *plan, const double *X, const double *u, const double *dU,
+                         double *gX, double *gu, void *stream) {
+    IP_TRY(check_plan(plan));
+    if (plan->prec != IP_F64)
+        return (ipibm_set_error("derivatives need an IP_F64 plan"), IP_ERR_UNSUPPORTED);
+    if (!plan->has_grid) return arg_error("plan has no grid");
+    if (plan->N > 0 && (!X || !u || !dU)) return arg_error("NULL array");
+    if (!aligned(X, 8) || !aligned(u, 8) || !aligned(dU, 8) || !aligned(gX, 8) || !aligned(gu, 8))
+        return arg_error("misaligned array");
+    return launch_interp_vjp(plan, X, u, dU, gX, gu, (hipStream_t)stream);
+}
+
 ip_status ip_taylor(ip_plan *plan, const double *X, const double *Dstar, double *D,
                     double *loss, double *gX, void *stream) {
     IP_TRY(check_plan(plan));

@@ -193,6 +193,8 @@ ip_status launch_step_vjp(ip_plan *p, const double *X, const ip_reference *ref,
                           const ip_constants *k, const double *u, double dt,
                           const double *lam_in, double *lam_out, double *gk, double *gu,
                           hipStream_t s);
+ip_status launch_interp_vjp(ip_plan *p, const double *X, const double *u, const double *dU,
+                            double *gX, double *gu, hipStream_t s);
 ip_status launch_taylor(ip_plan *p, const double *X, const double *Dstar, double *D, double *loss,
                         double *gX, hipStream_t s);
 

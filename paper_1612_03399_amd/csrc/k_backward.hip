@@ -219,24 +219,15 @@ __device__ __forceinline__ int delta3_d(double s, double w[3], double dw[3]) {
 
 // lam = lam' + dt J_U^T P + c_b dF  (and X-independent pinned rows: lam = lam')
 // J_U[d][e] = dU_d/dX_e = sum over lattice d's 27 points of u_d * dw/dX_e.
-__global__ __launch_bounds__(256) void k_lambda(const double *__restrict__ X,
-                                                const double *__restrict__ u,
-                                                const double *__restrict__ lam_in,
-                                                const double *__restrict__ P,
-                                                const double *__restrict__ dF,
-                                                const int64_t *__restrict__ node_off, int B,
-                                                const double *__restrict__ mass, int64_t N, int nx,
-                                                int ny, int nz, double inv_h, double dt,
-                                                double *__restrict__ lam_out) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= N) return;
-    const int b = body_of(node_off, B, l);
-    const double c = dt * dt / mass[b];
-    const vec3<double> x = ldX(X, l), p = ldX(P, l);
+// g = J_U(x)^T p = sum_d p_d dU_d/dx: the gradient of the interpolated
+// velocity at x (3-point delta and its derivative per axis) dotted with p.
+__device__ __forceinline__ void interp_grad_dot(const vec3<double> &x, const vec3<double> &p,
+                                                const double *__restrict__ u, int nx, int ny,
+                                                int nz, double inv_h, double g[3]) {
     const double pd[3] = {p.x, p.y, p.z};
     const double xv[3] = {x.x, x.y, x.z};
     const int64_t plane = (int64_t)nx * ny, field = plane * nz;
-    double g[3] = {0.0, 0.0, 0.0};
+    g[0] = g[1] = g[2] = 0.0;
     for (int d = 0; d < 3; ++d) {
         double w[3][3], dw[3][3];
         int cc[3];
@@ -259,8 +250,38 @@ __global__ __launch_bounds__(256) void k_lambda(const double *__restrict__ X,
         g[1] += pd[d] * gy * inv_h;
         g[2] += pd[d] * gz * inv_h;
     }
+}
+
+__global__ __launch_bounds__(256) void k_lambda(const double *__restrict__ X,
+                                                const double *__restrict__ u,
+                                                const double *__restrict__ lam_in,
+                                                const double *__restrict__ P,
+                                                const double *__restrict__ dF,
+                                                const int64_t *__restrict__ node_off, int B,
+                                                const double *__restrict__ mass, int64_t N, int nx,
+                                                int ny, int nz, double inv_h, double dt,
+                                                double *__restrict__ lam_out) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    const int b = body_of(node_off, B, l);
+    const double c = dt * dt / mass[b];
+    double g[3];
+    interp_grad_dot(ldX(X, l), ldX(P, l), u, nx, ny, nz, inv_h, g);
     for (int e = 0; e < 3; ++e)
         lam_out[3 * l + e] = lam_in[3 * l + e] + dt * g[e] + c * dF[3 * l + e];
+}
+
+// gX = J_U^T dU per node (the adjoint of interpolation with respect to X).
+__global__ __launch_bounds__(256) void k_interp_vjp_x(const double *__restrict__ X,
+                                                      const double *__restrict__ u,
+                                                      const double *__restrict__ dU, int64_t N,
+                                                      int nx, int ny, int nz, double inv_h,
+                                                      double *__restrict__ gX) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= N) return;
+    double g[3];
+    interp_grad_dot(ldX(X, l), ldX(dU, l), u, nx, ny, nz, inv_h, g);
+    for (int e = 0; e < 3; ++e) gX[3 * l + e] = g[e];
 }
 
 // F := s P (spreading source for the u-gradient)
@@ -828,6 +849,26 @@ ip_status launch_step_vjp(ip_plan *p, const double *X, const ip_reference *ref,
                            dt * h * h * h, 3 * p->N, dF);
         IP_HIP_CHECK(hipGetLastError());
         return launch_spread(p, X, dF, gu, s);
+    }
+    return IP_OK;
+}
+
+ip_status launch_interp_vjp(ip_plan *p, const double *X, const double *u, const double *dU,
+                            double *gX, double *gu, hipStream_t s) {
+    if (p->N == 0) return IP_OK;
+    if (gX) {
+        hipLaunchKernelGGL(k_interp_vjp_x, dim3(nblocks(p->N, 256)), dim3(256), 0, s, X, u, dU,
+                           p->N, p->grid.nx, p->grid.ny, p->grid.nz, 1.0 / p->grid.h, gX);
+        IP_HIP_CHECK(hipGetLastError());
+    }
+    if (gu) {
+        // gu_d[k] += sum_l dU_l,d w_k(X_l) = spread(h^3 dU) (spreading divides by h^3)
+        const double h = p->grid.h;
+        double *tmp = (double *)p->Fbuf;
+        hipLaunchKernelGGL(k_scale, dim3(nblocks(3 * p->N, 256)), dim3(256), 0, s, dU, h * h * h,
+                           3 * p->N, tmp);
+        IP_HIP_CHECK(hipGetLastError());
+        return launch_spread(p, X, tmp, gu, s);
     }
     return IP_OK;
 }

@@ -79,6 +79,7 @@ def _load():
         "ip_forces_jvp": [vp, vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp],
         "ip_plan_bind_reference": [vp, C.POINTER(ip_reference), vp],
         "ip_plan_bind_edge_weights": [vp, vp, vp],
+        "ibm_interp_vjp": [vp, vp, vp, vp, vp, vp, vp],
         "ip_step_vjp": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, d, vp, vp,
                         vp, vp, vp],
         "ip_taylor": [vp, vp, vp, vp, vp, vp, vp],
@@ -350,6 +351,16 @@ def ip_taylor(plan: Plan, X, Dstar=None, stream=None):
     _check(LIB.ip_taylor(plan.handle, _ptr(X), _ptr(Dstar), _ptr(D), _ptr(loss), _ptr(gX),
                          _stream(stream)))
     return D, loss, gX
+
+
+def ibm_interp_vjp(plan: Plan, X, u, dU, gX=None, gu=None, want_gX=True, stream=None):
+    """Adjoint of ibm_interp: returns (gX = J_U^T dU [N][3], gu); gu is
+    accumulated into when given (the caller zeroes it), skipped when None."""
+    if gX is None and want_gX:
+        gX = torch.empty(plan.N, 3, dtype=torch.float64, device=X.device)
+    _check(LIB.ibm_interp_vjp(plan.handle, _ptr(X), _ptr(u), _ptr(dU), _ptr(gX), _ptr(gu),
+                              _stream(stream)))
+    return gX, gu
 
 
 def ip_plan_bind_edge_weights(plan: Plan, ew, stream=None):

@@ -173,3 +173,41 @@ def test_derivatives_need_f64():
     with pytest.raises(N.IpibmError) as e:
         N.ip_forces_jvp(plan, X, X, gref, constants(wl))
     assert e.value.code == N.IP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("case", ["drop_L3_64", "four_L2_32", "ventricle_small"])
+def test_interp_vjp_parity(case):
+    """ibm_interp_vjp against the oracle: gX = J_U^T dU from the oracle's
+    interpolation Jacobian, gu = h^3 spread(dU) (the transpose of
+    interpolation), accumulated onto a seeded gu."""
+    say("interp_vjp", case)
+    wl, ref, plan, gref, k = setup(case)
+    u = wl.velocity(dtype=np.float64)
+    rng = np.random.default_rng(31)
+    dU = rng.normal(size=wl.X.shape)
+    J = O.interp_jac(wl.X, wl.grid, u)
+    want_gX = np.einsum("lde,ld->le", J, dU)
+    want_gu = wl.grid.h ** 3 * O.spread(wl.X, dU, wl.grid)
+    gu0 = rng.normal(size=u.shape) * np.abs(want_gu).max()
+    gu = dev(gu0)
+    gX, _ = N.ibm_interp_vjp(plan, dev(wl.X), dev(u), dev(dU), gu=gu)
+    e_x = per_body_rel(host(gX), want_gX, wl.node_off)
+    e_u = rel_inf(host(gu) - gu0, want_gu)
+    say(f"  gX {e_x:.2e}  gu {e_u:.2e}")
+    assert e_x <= TOL and e_u <= TOL
+    # the adjoint identity <dU, I(X) v> = <I^T dU, v> for a random field v
+    v = rng.normal(size=u.shape)
+    Iv = host(N.ibm_interp(plan, dev(wl.X), dev(v)))
+    gv = torch.zeros(u.shape, dtype=torch.float64, device=DEV)
+    N.ibm_interp_vjp(plan, dev(wl.X), dev(u), dev(dU), gu=gv, want_gX=False)
+    lhs, rhs = (dU * Iv).sum(), (host(gv) * v).sum()
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(dU * Iv).sum()
+
+
+def test_interp_vjp_needs_f64():
+    wl = CASES["drop_L3_64"]()
+    plan = N.Plan(wl, wl.grid, "f32")
+    X = dev(wl.X)
+    u = dev(wl.velocity(dtype=np.float64))
+    with pytest.raises(N.IpibmError):
+        N.ibm_interp_vjp(plan, X, u, X)
