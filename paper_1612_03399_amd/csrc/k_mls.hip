@@ -707,7 +707,7 @@ static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArg
     return IP_OK;
 }
 
-constexpr int kMlsThreads = 512;
+constexpr int kMlsThreads = 768;
 
 ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double alpha, void *U,
                             hipStream_t s) {
