@@ -14,6 +14,7 @@ from paper_1612_03399_amd import native as N
 from paper_1612_03399_amd import workload as W
 
 from gpu_common import DEV, TOL, dev, host, rel_inf
+from test_gpu_unfused import sheet_and_drop
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +28,9 @@ CASES = {
     # first corner
     "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
                                            cells_per_unit=96),
+    # a plan without fused work units: spreading and direct forcing take the
+    # per-marker kernels with device atomics
+    "unfused_sheet_drop": sheet_and_drop,
 }
 
 
