@@ -16,7 +16,7 @@
 //
 // The per-axis parts are shared: along any axis the three MAC lattices sit at
 // only two offsets (integer or half cells), so a marker computes six axes for
-// all three lattices; the three weights of an axis take two exponentials
+// all three lattices (the probe kernel excepted, see there); the three weights of an axis take two exponentials
 // (w_{c-1,c+1} = w_c exp(-q^2) exp(+-2 d_c q^2)); and the Cholesky factor keeps
 // the reciprocals of its diagonal, so each solve is four divisions.
 //
@@ -412,6 +412,9 @@ __global__ __launch_bounds__(256) void k_probe_loads(
         const vec3<double> y{xc.x + sg * g.h * nu.x, xc.y + sg * g.h * nu.y, xc.z + sg * g.h * nu.z};
         // the pressure lattice (cell centres) takes the half-cell axes on
         // all three axes; velocity lattice i the integer one along axis i
+        // each fit computes its own axes: their exponentials overlap that
+        // fit's 27 gathers (sharing the half-cell axes across the four fits
+        // leaves the gathers exposed and measured slower)
         double ap[4], G[3][3];
         {
             MlsAxis X, Y, Z;
