@@ -170,6 +170,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
                                        p->device));
     if (lds_optin <= 0) IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin,
                                      hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+    p->lds_optin = lds_optin;
     // threads: 0 = large units on 768-thread workgroups and units of at most
     // 384 x 4 nodes on 384-thread ones (two per compute unit); 768 or 384 =
     // every unit on that size
@@ -264,6 +265,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
             if (!pb.empty()) IP_TRY(alloc_bytes((void **)&p->Xstage, (size_t)N * 3 * sizeof(double)));
             IP_TRY(prepare_step_fused(p));
             if (p->prec == IP_F64) IP_TRY(prepare_step_vjp_fused(p));
+            if (p->has_grid) IP_TRY(prepare_mls_units(p));
         }
     }
     IP_HIP_CHECK(hipDeviceSynchronize());

@@ -69,6 +69,7 @@ struct ip_plan {
     bool fused_all = false;
     int fused_nmax = 0;           // largest work unit (nodes, owned + halo)
     int fused_tile_bytes = 0;     // LDS bytes for the grid tile (first launch class)
+    int lds_optin = 0;            // LDS bytes one workgroup may use on this device
     int step_threads = 768;       // threads per workgroup (first launch class)
     // launch classes of the fused step: consecutive ranges of the units
     // (largest first), each with its own workgroup size and LDS layout
@@ -205,6 +206,7 @@ constexpr int kStepFacesPerThread = 8;   // faces held in registers per thread
 constexpr int kPatchOwned = 512;         // owned nodes per patch of a large body
 size_t step_fused_lds_bytes(int nmax, int tile_bytes);
 ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
+ip_status prepare_mls_units(ip_plan *p);    // one-time launch attributes
 ip_status launch_bind_edge_weights(ip_plan *p, const double *ew, hipStream_t s);
 ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s);
 // owned nodes of patched units: src -> dst ([N][3] double each)

@@ -690,9 +690,7 @@ MlsGrid mls_grid(const ip_plan *p, double alpha) {
 // largest tile that fits beside them (1 KB kept for the static LDS).
 static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArgs &a,
                            size_t &lds) {
-    int lds_optin = 0;
-    IP_HIP_CHECK(hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                                       p->device));
+    const int lds_optin = p->lds_optin;
     a.X = X;
     a.g = mls_grid(p, alpha);
     a.status = p->status;
@@ -711,6 +709,25 @@ static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArg
 }
 
 constexpr int kMlsThreads = 768;
+
+// Launch attributes of the per-unit kernels (their dynamic LDS), set once when
+// the plan is built, so that the launches themselves can be captured.
+template <typename R>
+static ip_status set_unit_attributes(size_t lds) {
+    const void *fns[2] = {(const void *)k_spread_mls_units<R, kMlsThreads, false>,
+                          (const void *)k_spread_mls_units<R, kMlsThreads, true>};
+    for (const void *fn : fns)
+        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return IP_OK;
+}
+
+ip_status prepare_mls_units(ip_plan *p) {
+    if (!p->fused_all || p->n_units == 0) return IP_OK;
+    MlsUnitArgs a{};
+    size_t lds = 0;
+    IP_TRY(unit_args(p, nullptr, 1.0, a, lds));
+    return p->prec == IP_F64 ? set_unit_attributes<double>(lds) : set_unit_attributes<float>(lds);
+}
 
 ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double alpha, void *U,
                             hipStream_t s) {
@@ -737,9 +754,6 @@ ip_status launch_spread_mls(ip_plan *p, const double *X, const void *Fm, double 
         IP_TRY(unit_args(p, X, alpha, a, lds));
         a.Fm = Fm;
         a.f = f;
-        const void *fn = p->prec == IP_F64 ? (const void *)k_spread_mls_units<double, kMlsThreads, false>
-                                           : (const void *)k_spread_mls_units<float, kMlsThreads, false>;
-        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         if (p->prec == IP_F64)
             hipLaunchKernelGGL((k_spread_mls_units<double, kMlsThreads, false>), dim3(p->n_units),
                                dim3(kMlsThreads), lds, s, a);
@@ -773,9 +787,6 @@ ip_status launch_direct_forcing_mls(ip_plan *p, const double *X, const void *Vb,
         a.Fout = Fout;
         a.inv_dt = 1.0 / dt;
         a.f = f;
-        const void *fn = p->prec == IP_F64 ? (const void *)k_spread_mls_units<double, kMlsThreads, true>
-                                           : (const void *)k_spread_mls_units<float, kMlsThreads, true>;
-        IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         if (p->prec == IP_F64)
             hipLaunchKernelGGL((k_spread_mls_units<double, kMlsThreads, true>), dim3(p->n_units),
                                dim3(kMlsThreads), lds, s, a);

@@ -65,3 +65,60 @@ def test_graph_replays_match_eager(case):
         assert step_error(wl, Xe2, Xe, wl.X, 1e-12) <= 1.0
     code, flags = N.ip_plan_status(plan)
     assert code == N.IP_OK, flags
+
+
+@pytest.mark.parametrize("case", ["four_L4_128", "ventricle_patched"])
+def test_graph_replays_of_the_centroid_transfers(case):
+    """MLS interpolation, one-pass direct forcing and probe loads captured
+    together: every replay gives the eager results (spreading to rounding)."""
+    say("graph mls", case)
+    wl = (W.small_suspension(4, 4, 128, r=0.04) if case == "four_L4_128"
+          else W.config3(freq=40, leaflet_quads=30, noise_rel=0.2, cells_per_unit=96))
+    plan = N.Plan(wl, wl.grid, "f64")
+    rng = np.random.default_rng(8)
+    X = dev(wl.X)
+    u = dev(wl.velocity())
+    p = dev(rng.normal(size=(wl.grid.nz, wl.grid.ny, wl.grid.nx)))
+    Vb = dev(rng.normal(scale=0.1, size=(wl.n_faces, 3)))
+    acc = dev(rng.normal(size=(wl.n_faces, 3)))
+    alpha, dt, mu = 0.4, 1e-3, 0.02
+    F = wl.n_faces
+
+    def run(U, Fm, f, Fext, stream=None):
+        N.ibm_interp_mls(plan, X, u, alpha, U, stream=stream)
+        N.ibm_direct_forcing_mls(plan, X, Vb, u, alpha, dt, f, Fm=Fm, stream=stream)
+        N.ibm_probe_loads(plan, X, u, p, alpha, mu, acc=acc, Fext=Fext, stream=stream)
+
+    bufs = lambda: (torch.empty(F, 3, dtype=torch.float64, device=DEV),
+                    torch.empty(F, 3, dtype=torch.float64, device=DEV),
+                    torch.zeros_like(u), torch.empty(F, 3, dtype=torch.float64, device=DEV))
+    Ue, Fme, fe, Fxe = bufs()
+    run(Ue, Fme, fe, Fxe)
+    torch.cuda.synchronize()
+    Ue, Fme, fe, Fxe = host(Ue), host(Fme), host(fe), host(Fxe)
+    Ug, Fmg, fg, Fxg = bufs()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        run(Ug, Fmg, fg, Fxg, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in (Ug, Fmg, Fxg):
+            t.fill_(7.0)
+        fg.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(Ug), Ue) and np.array_equal(host(Fmg), Fme)
+        assert np.array_equal(host(Fxg), Fxe)
+        e_f = rel_inf(host(fg), fe)
+        say(f"  replay {rep}: U, Fm, Fext identical, f {e_f:.2e}")
+        assert e_f <= 1e-12
+        # eager work between replays
+        a, b, c, d = bufs()
+        run(a, b, c, d)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(a), Ue)
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
