@@ -234,17 +234,20 @@ __device__ __forceinline__ void interp_grad_dot(const vec3<double> &x, const vec
         for (int ax = 0; ax < 3; ++ax)
             cc[ax] = delta3_d(xv[ax] * inv_h - mac_off(d, ax), w[ax], dw[ax]);
         const double *ud = u + d * field;
+        const int ix[3] = {wrapi(cc[0] - 1, nx), wrapi(cc[0], nx), wrapi(cc[0] + 1, nx)};
         double gx = 0.0, gy = 0.0, gz = 0.0;
+        // separable: per (y, z) row the x-sums with w and dw, then the row's
+        // weights for each component
         for (int kz = 0; kz < 3; ++kz)
             for (int ky = 0; ky < 3; ++ky) {
                 const double *row = ud + wrapi(cc[2] - 1 + kz, nz) * plane +
                                     (int64_t)wrapi(cc[1] - 1 + ky, ny) * nx;
-                for (int kx = 0; kx < 3; ++kx) {
-                    const double uv = row[wrapi(cc[0] - 1 + kx, nx)];
-                    gx += uv * dw[0][kx] * w[1][ky] * w[2][kz];
-                    gy += uv * w[0][kx] * dw[1][ky] * w[2][kz];
-                    gz += uv * w[0][kx] * w[1][ky] * dw[2][kz];
-                }
+                const double u0 = row[ix[0]], u1 = row[ix[1]], u2 = row[ix[2]];
+                const double rw = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+                const double rd = u0 * dw[0][0] + u1 * dw[0][1] + u2 * dw[0][2];
+                gx += rd * (w[1][ky] * w[2][kz]);
+                gy += rw * (dw[1][ky] * w[2][kz]);
+                gz += rw * (w[1][ky] * dw[2][kz]);
             }
         g[0] += pd[d] * gx * inv_h;
         g[1] += pd[d] * gy * inv_h;
@@ -708,34 +711,34 @@ __global__ __launch_bounds__(NT) void k_step_vjp_fused(VjpArgs a) {
                     lz + 2 >= tg.Tz) {
                     bad = true;
                 } else {
+                    // separable: per (y, z) row the x-sums with w and dw,
+                    // then the row's weights for each component
 #pragma unroll
                     for (int z = 0; z < 3; ++z)
 #pragma unroll
                         for (int y = 0; y < 3; ++y) {
                             const double *row = utile + ((lz + z) * tg.Ty + (ly + y)) * tg.Tx + lx;
-#pragma unroll
-                            for (int x = 0; x < 3; ++x) {
-                                const double uv = row[x];
-                                gx += uv * dw[0][x] * w[1][y] * w[2][z];
-                                gy += uv * w[0][x] * dw[1][y] * w[2][z];
-                                gz += uv * w[0][x] * w[1][y] * dw[2][z];
-                            }
+                            const double rw = row[0] * w[0][0] + row[1] * w[0][1] + row[2] * w[0][2];
+                            const double rd = row[0] * dw[0][0] + row[1] * dw[0][1] + row[2] * dw[0][2];
+                            gx += rd * (w[1][y] * w[2][z]);
+                            gy += rw * (dw[1][y] * w[2][z]);
+                            gz += rw * (w[1][y] * dw[2][z]);
                         }
                 }
             } else {
+                const int ix[3] = {wrapi(cc[0] - 1, a.nx), wrapi(cc[0], a.nx), wrapi(cc[0] + 1, a.nx)};
 #pragma unroll
                 for (int z = 0; z < 3; ++z)
 #pragma unroll
                     for (int y = 0; y < 3; ++y) {
                         const double *row = ud + wrapi(cc[2] - 1 + z, a.nz) * a.plane +
                                             (int64_t)wrapi(cc[1] - 1 + y, a.ny) * a.nx;
-#pragma unroll
-                        for (int x = 0; x < 3; ++x) {
-                            const double uv = row[wrapi(cc[0] - 1 + x, a.nx)];
-                            gx += uv * dw[0][x] * w[1][y] * w[2][z];
-                            gy += uv * w[0][x] * dw[1][y] * w[2][z];
-                            gz += uv * w[0][x] * w[1][y] * dw[2][z];
-                        }
+                        const double u0 = row[ix[0]], u1 = row[ix[1]], u2 = row[ix[2]];
+                        const double rw = u0 * w[0][0] + u1 * w[0][1] + u2 * w[0][2];
+                        const double rd = u0 * dw[0][0] + u1 * dw[0][1] + u2 * dw[0][2];
+                        gx += rd * (w[1][y] * w[2][z]);
+                        gy += rw * (dw[1][y] * w[2][z]);
+                        gz += rw * (w[1][y] * dw[2][z]);
                     }
             }
             const double pd = dF[3 * p + d] * a.inv_h;    // P'_d d/dX = P'_d (1/h) d/ds
