@@ -385,7 +385,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in the design notes, not built.",
+              "a step sharded over several GPUs is not built.",
               file=sys.stderr)
         sys.exit(2)
 

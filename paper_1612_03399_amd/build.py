@@ -19,7 +19,8 @@ SOURCES = ["api.hip", "workunits.hip", "k_forces.hip", "k_transfer.hip", "k_mls.
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
     "-mcode-object-version=5",
-    # no packed-FP32 instructions (see the design notes on gfx950 builds)
+    # no packed-FP32 instructions: FP32 arithmetic stays on scalar-lane
+    # operations (packed forms have returned wrong results on gfx950)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
