@@ -89,10 +89,15 @@ def autotune(mesh, grid, precision, X, ref, k, u, dt, candidates=CANDIDATES, ste
                             "tile_bytes": plan.tile_bytes, "largest_unit": plan.largest_unit})
         finally:
             plan.close()
-    # earlier candidates win unless a later one is faster by more than the
-    # timing noise (2%)
+    return choose(results)["options"], results
+
+
+def choose(results, margin=0.02):
+    """The result to keep: candidates are listed in order of preference, and
+    a later one replaces the current choice only when it is faster by more
+    than `margin` (the timing noise)."""
     best = results[0]
     for r in results[1:]:
-        if r["ms"] < 0.98 * best["ms"]:
+        if r["ms"] < (1.0 - margin) * best["ms"]:
             best = r
-    return best["options"], results
+    return best
