@@ -189,8 +189,8 @@ ip_status ip_plan_bind_reference(ip_plan *plan, const ip_reference *ref, void *s
 /* Bind per-edge weights on the spring and bending constants (Section 2.3:
  * on meshes of non-uniform triangles the edge stiffness varies edge by edge;
  * the paper points to an external model for it and does not print the rule,
- * so the weights come from the caller).  ew: device double[E][2], (w_s, w_b)
- * for each edge in the mesh's edge order; edge e of body b then carries
+ * so the weights come from the caller).  ew: device double[E][2], 16-byte
+ * aligned, (w_s, w_b) for each edge in the mesh's edge order; edge e of body b then carries
  * ks[b] w_s[e] and kb[b] w_b[e] in every later call on the plan (forces,
  * energies, steps, their JVP and VJP; the constants' gradients are with
  * respect to the per-body ks, kb with the weights held fixed).  NULL unbinds
