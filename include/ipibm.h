@@ -7,6 +7,11 @@
  * bodies: interaction-potential forces (Section 2.3), transfer between the
  * Lagrangian nodes and the staggered Eulerian grid (Section 2.2) and the
  * explicit node update (Section 2.3, Newton's second law per vertex).
+ * Beside the step: the derivatives of its parts (forces JVP, interpolation
+ * adjoint, reverse step, Taylor loss), the transfer at the triangle centroids
+ * (MLS interpolation and spreading, direct forcing, external loads from
+ * normal probes, centroid forces to the vertices; Section 2.2) and per-edge
+ * weights on the spring and bending constants (Section 2.3).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
