@@ -270,3 +270,27 @@ def test_probe_loads_degenerate_face_and_empty_batch():
     out = N.ibm_probe_loads(plan, z, dev(u), dev(p), 0.4, 0.02)
     assert out.shape == (0, 3)
     assert N.ip_plan_status(plan)[0] == N.IP_OK
+
+
+def test_probe_loads_ventricle_full_size_sampled():
+    """The ventricle workload at full size (a closed shell and two open
+    leaflets, 240 000 faces, 384 x 384 x 512): one- and two-sided probes on
+    4000 sampled faces of each kind against the oracle."""
+    say("probe loads ventricle full size")
+    wl = W.config3()
+    u, p, acc = probe_inputs(wl, "f64")
+    plan = N.Plan(wl, wl.grid, "f64")
+    got = host(N.ibm_probe_loads(plan, dev(wl.X), dev(u), dev(p), 0.4, 1e-3, acc=dev(acc)))
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    fo = np.asarray(wl.face_off)
+    rng = np.random.default_rng(6)
+    for b in range(wl.n_bodies):
+        pick = np.sort(rng.choice(np.arange(fo[b], fo[b + 1]), min(4000, fo[b + 1] - fo[b]),
+                                  replace=False))
+        sub = types.SimpleNamespace(faces=np.asarray(wl.faces)[pick], closed=[wl.closed[b]],
+                                    face_off=[0, pick.size])
+        want = O.probe_loads(sub, wl.X, wl.grid, u, p, 0.4, 1e-3, acc=acc[pick])
+        e = rel_inf(got[pick], want)
+        say(f"  body {b} ({'closed' if wl.closed[b] else 'open'}): {e:.2e}")
+        assert e <= TOL["f64"]
