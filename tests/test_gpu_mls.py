@@ -294,3 +294,31 @@ def test_probe_loads_ventricle_full_size_sampled():
         e = rel_inf(got[pick], want)
         say(f"  body {b} ({'closed' if wl.closed[b] else 'open'}): {e:.2e}")
         assert e <= TOL["f64"]
+
+
+def test_mls_ventricle_full_size():
+    """MLS interpolation on sampled markers and spreading by its conservation
+    law on the full-size ventricle, whose 100 002-node shell runs as patches."""
+    say("mls ventricle full size")
+    wl = W.config3()
+    alpha = 0.4
+    u = wl.velocity()
+    plan = N.Plan(wl, wl.grid, "f64")
+    assert plan.patched_bodies > 0
+    X = dev(wl.X)
+    U = host(N.ibm_interp_mls(plan, X, dev(u), alpha))
+    Cc, Af = O.centroids(wl, wl.X)
+    pick = np.random.default_rng(19).choice(wl.n_faces, 4000, replace=False)
+    e_u = rel_inf(U[pick], O.interp_mls(Cc[pick], wl.grid, u, alpha))
+    Fm = np.random.default_rng(20).normal(size=(wl.n_faces, 3))
+    f = torch.zeros(u.shape, dtype=torch.float64, device=DEV)
+    N.ibm_spread_mls(plan, X, dev(Fm), alpha, f)
+    code, flags = N.ip_plan_status(plan)
+    assert code == N.IP_OK, flags
+    h = wl.grid.h
+    tot = host(f.sum(dim=(1, 2, 3))) * h ** 3
+    want = ((Af * h)[:, None] * Fm).sum(axis=0)
+    scale = np.abs((Af * h)[:, None] * Fm).sum(axis=0)
+    e_c = np.abs(tot - want).max() / scale.max()
+    say(f"  U sampled {e_u:.2e}  conservation {e_c:.2e}")
+    assert e_u <= TOL["f64"] and e_c <= 1e-12
