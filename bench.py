@@ -377,8 +377,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other-precision, graph, differentiation and uneven legs")
-    ap.add_argument("--legs", default="other,backward,uneven,mls",
-                    help="extra legs to run: other (other precision + hipGraph), backward, "
+    ap.add_argument("--legs", default="other,weights,backward,uneven,mls",
+                    help="extra legs to run: other (other precision + hipGraph), weights "
+                         "(per-edge weights bound), backward, "
                          "uneven, mls (MLS transfer at the triangle centroids)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
@@ -524,6 +525,25 @@ def main():
         extras[f"{other}_graph_ms_per_step"] = e0.elapsed_time(e1) / (10 * reps)
         log(f"{other} graph replay: {extras[f'{other}_graph_ms_per_step']:.4f} ms/step")
         del g, plan2, X2, u2, f2
+        torch.cuda.empty_cache()
+    if "weights" in legs:
+        # per-edge weights on ks and kb bound to a plan of the same shape: the
+        # weighted kernel reads one more 16-byte value per edge record
+        plan3, ref3, k3, X3, u3, f3, V3, A3 = setup(args.precision)
+        gw = torch.Generator(device=dev)
+        gw.manual_seed(1003)
+        ew = 0.5 + 1.5 * torch.rand((wl.n_edges, 2), generator=gw, device=dev,
+                                    dtype=torch.float64)
+        N.ip_plan_bind_edge_weights(plan3, ew)
+        ms3 = time_steps(N, plan3, X3, ref3, k3, u3, f3, wl.dt, V3, A3, args.steps,
+                         args.warmup, stream, torch)
+        code, flags = N.ip_plan_status(plan3)
+        if code != N.IP_OK:
+            raise SystemExit(f"device status {code} flags {flags} in the weights leg")
+        extras["edge_weights_ms_per_step"] = ms3
+        extras["edge_weights_over_unweighted"] = ms3 / ms
+        log(f"per-edge weights bound: {ms3:.4f} ms/step ({ms3 / ms:.3f}x the unweighted step)")
+        del plan3, X3, u3, f3, ew
         torch.cuda.empty_cache()
     if "backward" in legs and args.precision == "f64":
         extras.update(backward_leg(N, W, args.bodies, dev, torch, log))
