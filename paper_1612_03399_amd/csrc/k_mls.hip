@@ -708,6 +708,8 @@ static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArg
     return IP_OK;
 }
 
+// One workgroup per unit fills the LDS with its tile, so the workgroup size
+// sets the waves per SIMD: 768 threads give 3 (512 gave 2 and were slower).
 constexpr int kMlsThreads = 768;
 
 // Launch attributes of the per-unit kernels (their dynamic LDS), set once when
