@@ -5,6 +5,7 @@ import torch
 
 import oracle as O
 from paper_1612_03399_amd import native as N
+from paper_1612_03399_amd import workload as W
 from paper_1612_03399_amd.workload import subset  # noqa: F401  (re-exported for the tests)
 
 DEV = "cuda"
@@ -83,3 +84,42 @@ def step_error(wl, Xg, Xo, X0, tol):
         ulp = np.spacing(np.abs(X0[s]).max())
         worst = max(worst, np.abs(Xg[s] - Xo[s]).max() / (tol * dx + 2 * ulp))
     return worst
+
+
+def body_spheres(wl):
+    c = np.empty((wl.n_bodies, 3))
+    r = np.empty(wl.n_bodies)
+    for b in range(wl.n_bodies):
+        x = wl.X[wl.node_off[b]:wl.node_off[b + 1]]
+        c[b] = x.mean(axis=0)
+        r[b] = np.sqrt(((x - c[b]) ** 2).sum(axis=1).max())
+    return c, r
+
+
+def support_mask(X, grid):
+    """Points of the three lattices within the 27-point supports of X."""
+    n = np.array([grid.nx, grid.ny, grid.nz])
+    m = np.zeros((3, grid.nz, grid.ny, grid.nx), bool)
+    for d in range(3):
+        off = np.array(W.MAC_OFFSETS[d])
+        c = np.floor(X / grid.h - off + 0.5).astype(np.int64)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    i = (c + np.array([dx, dy, dz])) % n
+                    m[d, i[:, 2], i[:, 1], i[:, 0]] = True
+    return m
+
+
+def near_bodies(wl, sample, extra_cells=3.0):
+    """Sorted ids of the bodies whose grid support can reach that of a body in
+    `sample` (bounding spheres about the node mean, grown by extra_cells grid
+    spacings; unit periodic box)."""
+    c, r = body_spheres(wl)
+    reach = r + extra_cells * wl.grid.h
+    near = set()
+    for b in sample:
+        d = c - c[b]
+        d -= np.round(d)
+        near |= set(np.flatnonzero(np.sqrt((d * d).sum(axis=1)) < reach + reach[b]).tolist())
+    return sorted(near)

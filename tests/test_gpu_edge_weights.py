@@ -58,7 +58,7 @@ def test_weighted_forces_parity(case, precision):
     e_w = elem_rel(host(Wt), want["W"])
     say(f"  F {e_f:.2e}  W {e_w:.2e}")
     assert e_f <= TOL[precision]
-    assert e_w <= (1e-10 if precision == "f64" else 1e-6)
+    assert e_w <= (1e-12 if precision == "f64" else 1e-6)
 
 
 def weighted_step(wl, ref, precision, ew, options=None):

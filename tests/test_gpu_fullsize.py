@@ -12,8 +12,8 @@ import oracle as O
 from paper_1612_03399_amd import native as N
 from paper_1612_03399_amd import workload as W
 
-from gpu_common import (DEV, TOL, constants, dev, gpu_reference_from_oracle, host,
-                        oracle_reference_as_seen, rel_inf, step_error, subset)
+from gpu_common import (DEV, TOL, constants, dev, gpu_reference_from_oracle, host, near_bodies,
+                        oracle_reference_as_seen, rel_inf, step_error, subset, support_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -22,10 +22,10 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_step(wl, ref, u, precision, bound=True):
+def gpu_step(wl, ref, u, precision, bound=True, options=None):
     """One ip_step as the bench runs it: reference bound to the plan."""
     rdt = N.real_dtype(precision)
-    plan = N.Plan(wl, wl.grid, precision)
+    plan = N.Plan(wl, wl.grid, precision, options)
     X = dev(wl.X)
     f = torch.zeros(u.shape, dtype=rdt, device=DEV)
     V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
@@ -78,29 +78,35 @@ def test_ventricle_full_step():
     assert pin.any() and np.array_equal(Xg[pin], wl.X[pin])
 
 
-def body_spheres(wl):
-    c = np.empty((wl.n_bodies, 3))
-    r = np.empty(wl.n_bodies)
-    for b in range(wl.n_bodies):
-        x = wl.X[wl.node_off[b]:wl.node_off[b + 1]]
-        c[b] = x.mean(axis=0)
-        r[b] = np.sqrt(((x - c[b]) ** 2).sum(axis=1).max())
-    return c, r
-
-
-def support_mask(X, grid):
-    """Points of the three lattices within the 27-point supports of X."""
-    n = np.array([grid.nx, grid.ny, grid.nz])
-    m = np.zeros((3, grid.nz, grid.ny, grid.nx), bool)
-    for d in range(3):
-        off = np.array(W.MAC_OFFSETS[d])
-        c = np.floor(X / grid.h - off + 0.5).astype(np.int64)
-        for dz in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dx in (-1, 0, 1):
-                    i = (c + np.array([dx, dy, dz])) % n
-                    m[d, i[:, 2], i[:, 1], i[:, 0]] = True
-    return m
+def uneven_sampled_check(wl, ref, u, options, per_level=16, seed=17):
+    """One fused step of the whole uneven batch with the given launch options;
+    the new positions of per_level sampled bodies of each level against the
+    oracle stepping them alone, and the grid force on the supports of the
+    sampled bodies against the oracle stepping every body whose support can
+    reach theirs."""
+    plan, Xg, fg, Vg, Ag = gpu_step(wl, ref, u, "f32", options=options)
+    levels = wl.extra["levels"]
+    rng = np.random.default_rng(seed)
+    sample = np.sort(np.concatenate([rng.choice(np.flatnonzero(levels == L), per_level,
+                                                replace=False) for L in (2, 3, 4, 5)]))
+    sizes = np.diff(np.asarray(wl.node_off))
+    say(f"  options {options}: {plan.n_units} units, {plan.patched_bodies} patched bodies; "
+        f"sample of {len(sample)} bodies, {int((sizes[sample] > 3072).sum())} of them level 5")
+    sub = subset(wl, sample)
+    want = O.step(sub, sub.X, oracle_reference_as_seen(O.reference(sub), "f32"), u, wl.dt,
+                  np.zeros_like(u))
+    Xg_s = np.concatenate([Xg[wl.node_off[b]:wl.node_off[b + 1]] for b in sample])
+    e_x = step_error(sub, Xg_s, want["X"], sub.X, TOL["f32"])
+    # grid force around the sampled bodies: every body whose support can reach
+    near = near_bodies(wl, sample)
+    nsub = subset(wl, near)
+    f_want = np.zeros_like(u)
+    O.step(nsub, nsub.X, oracle_reference_as_seen(O.reference(nsub), "f32"), u, wl.dt, f_want)
+    m = support_mask(sub.X, wl.grid)
+    e_f = rel_inf(fg[m], f_want[m])
+    say(f"  X {e_x:.3f} (<= 1)  f {e_f:.2e} over {m.sum()} points, {len(near)} bodies")
+    assert e_x <= 1.0 and e_f <= TOL["f32"]
+    return plan
 
 
 def test_uneven_full_sampled():
@@ -109,34 +115,8 @@ def test_uneven_full_sampled():
     ref = O.reference(wl)
     say(f"  {wl.n_bodies} bodies, {wl.n_nodes} nodes; velocity ...")
     u = wl.velocity(dtype=np.float32).astype(np.float64)
-    plan, Xg, fg, Vg, Ag = gpu_step(wl, ref, u, "f32")
-    say("  gpu done; sampled oracle ...")
-    rng = np.random.default_rng(17)
-    levels = wl.extra["levels"]
-    sample = np.concatenate([rng.choice(np.flatnonzero(levels == L), 2, replace=False)
-                             for L in (2, 3, 4, 5)])
-    oref = oracle_reference_as_seen(ref, "f32")
-    sub = subset(wl, sample)
-    want = O.step(sub, sub.X, oracle_reference_as_seen(O.reference(sub), "f32"), u, wl.dt,
-                  np.zeros_like(u))
-    Xg_s = np.concatenate([Xg[wl.node_off[b]:wl.node_off[b + 1]] for b in sample])
-    e_x = step_error(sub, Xg_s, want["X"], sub.X, TOL["f32"])
-    # grid force around the sampled bodies: every body whose support can reach
-    c, r = body_spheres(wl)
-    reach = r + 3.0 * wl.grid.h
-    near = set()
-    for b in sample:
-        d = c - c[b]
-        d -= np.round(d)                     # unit periodic box
-        near |= set(np.flatnonzero(np.sqrt((d * d).sum(axis=1)) < reach + reach[b]).tolist())
-    nsub = subset(wl, sorted(near))
-    f_want = np.zeros_like(u)
-    O.step(nsub, nsub.X, oracle_reference_as_seen(O.reference(nsub), "f32"), u, wl.dt, f_want)
-    m = support_mask(sub.X, wl.grid)
-    e_f = rel_inf(fg[m], f_want[m])
-    say(f"  X {e_x:.3f} (<= 1)  f {e_f:.2e} over {m.sum()} points, {len(near)} bodies")
-    assert e_x <= 1.0 and e_f <= TOL["f32"]
-    del oref
+    plan = uneven_sampled_check(wl, ref, u, None)
+    assert plan.patched_bodies > 0      # the level-5 bodies run as patches
 
 
 def test_rollout_gradient_full_size():

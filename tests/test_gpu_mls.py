@@ -13,7 +13,7 @@ import oracle as O
 from paper_1612_03399_amd import native as N
 from paper_1612_03399_amd import workload as W
 
-from gpu_common import DEV, TOL, dev, host, rel_inf
+from gpu_common import DEV, TOL, dev, host, near_bodies, rel_inf, subset, support_mask
 from test_gpu_unfused import sheet_and_drop
 
 pytestmark = pytest.mark.gpu
@@ -99,14 +99,18 @@ def test_mls_rejects_bad_alpha():
 
 
 def test_mls_full_size_sampled():
-    """The 1000-drop batch (5.12 M markers on 256^3): interpolation on 4000
-    sampled markers against the oracle, and spreading by its conservation
-    law sum_k f_d[k] h^3 = sum_l A_l h F_{l,d} over the whole batch."""
+    """The 1000-drop batch (5.12 M markers on 256^3), in the launch
+    configuration of the step: interpolation on 4000 sampled markers against
+    the oracle; spreading of every marker's force compared point by point on
+    the supports of 12 sampled drops against the oracle spreading the markers
+    of every drop whose support can reach them; and the conservation law
+    sum_k f_d[k] h^3 = sum_l A_l h F_{l,d} over the whole batch."""
     say("mls full size")
     wl = W.config1()
     alpha = 0.4
     u = wl.velocity()
     plan = N.Plan(wl, wl.grid, "f64")
+    assert plan.fused
     X = dev(wl.X)
     U = host(N.ibm_interp_mls(plan, X, dev(u), alpha))
     Cc, Af = O.centroids(wl, wl.X)
@@ -117,13 +121,23 @@ def test_mls_full_size_sampled():
     N.ibm_spread_mls(plan, X, dev(Fm), alpha, f)
     code, flags = N.ip_plan_status(plan)
     assert code == N.IP_OK, flags
+    fg = host(f)
     h = wl.grid.h
-    tot = host(f.sum(dim=(1, 2, 3))) * h ** 3
+    tot = fg.sum(axis=(1, 2, 3)) * h ** 3
     want = ((Af * h)[:, None] * Fm).sum(axis=0)
     scale = np.abs((Af * h)[:, None] * Fm).sum(axis=0)
     e_c = np.abs(tot - want).max() / scale.max()
-    say(f"  U sampled {e_u:.2e}  conservation {e_c:.2e}")
-    assert e_u <= TOL["f64"] and e_c <= 1e-12
+    # point by point on the supports of sampled drops
+    sample = np.sort(np.random.default_rng(21).choice(wl.n_bodies, 12, replace=False))
+    near = near_bodies(wl, sample)
+    fo = np.asarray(wl.face_off)
+    sel = np.concatenate([np.arange(fo[b], fo[b + 1]) for b in near])
+    f_want = O.spread_mls(Cc[sel], Af[sel], Fm[sel], wl.grid, alpha)
+    m = support_mask(Cc[np.concatenate([np.arange(fo[b], fo[b + 1]) for b in sample])], wl.grid)
+    e_f = rel_inf(fg[m], f_want[m])
+    say(f"  U sampled {e_u:.2e}  f {e_f:.2e} over {m.sum()} points ({len(near)} drops)  "
+        f"conservation {e_c:.2e}")
+    assert e_u <= TOL["f64"] and e_f <= TOL["f64"] and e_c <= 1e-12
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -297,8 +311,9 @@ def test_probe_loads_ventricle_full_size_sampled():
 
 
 def test_mls_ventricle_full_size():
-    """MLS interpolation on sampled markers and spreading by its conservation
-    law on the full-size ventricle, whose 100 002-node shell runs as patches."""
+    """MLS interpolation on sampled markers and spreading of every marker's
+    force, compared point by point over the whole field, on the full-size
+    ventricle, whose 100 002-node shell runs as patches."""
     say("mls ventricle full size")
     wl = W.config3()
     alpha = 0.4
@@ -315,10 +330,8 @@ def test_mls_ventricle_full_size():
     N.ibm_spread_mls(plan, X, dev(Fm), alpha, f)
     code, flags = N.ip_plan_status(plan)
     assert code == N.IP_OK, flags
-    h = wl.grid.h
-    tot = host(f.sum(dim=(1, 2, 3))) * h ** 3
-    want = ((Af * h)[:, None] * Fm).sum(axis=0)
-    scale = np.abs((Af * h)[:, None] * Fm).sum(axis=0)
-    e_c = np.abs(tot - want).max() / scale.max()
-    say(f"  U sampled {e_u:.2e}  conservation {e_c:.2e}")
-    assert e_u <= TOL["f64"] and e_c <= 1e-12
+    say("  gpu done; oracle spreading ...")
+    f_want = O.spread_mls(Cc, Af, Fm, wl.grid, alpha)
+    e_f = rel_inf(host(f), f_want)
+    say(f"  U sampled {e_u:.2e}  f {e_f:.2e} (whole field)")
+    assert e_u <= TOL["f64"] and e_f <= TOL["f64"]

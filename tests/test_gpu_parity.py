@@ -77,9 +77,10 @@ def test_forces_parity(case, precision):
     assert code == N.IP_OK
     tol = TOL[precision]
     assert per_body_rel(F, want["F"], wl.node_off) <= tol
-    assert elem_rel(V[wl.closed == 1], want["V"][wl.closed == 1]) <= (1e-12 if precision == "f64" else 1e-7)
+    # V is FP64 in both precisions
+    assert elem_rel(V[wl.closed == 1], want["V"][wl.closed == 1]) <= 1e-12
     assert elem_rel(A, want["A"]) <= tol
-    assert elem_rel(Wg, want["W"]) <= (1e-10 if precision == "f64" else 1e-6)
+    assert elem_rel(Wg, want["W"]) <= (1e-12 if precision == "f64" else 1e-6)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])

@@ -182,6 +182,33 @@ def test_hinge_angle_hand_built():
         assert abs(th - want) < 1e-15
 
 
+def test_hinge_energy_closed_form():
+    """W_b of one hinge folded by a known angle d from its reference fold:
+    k_b (1 - cos d), against the power series of 1 - cos d (small d, where
+    the direct difference 1 - cos d loses about 1e-16 / d^2 of its value) and
+    exact values at large d.  Springs and areas are switched off."""
+    kb = 0.7
+    faces = [[0, 1, 2], [1, 0, 3]]
+
+    def hinge(phi):
+        return np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0],
+                         [0, -math.cos(phi), -math.sin(phi)]], float)
+
+    k = [[0.0], [kb], [0.0], [0.0]]
+    for th0 in (0.0, math.pi / 4):
+        for d in (1e-6, 1e-4, 3e-2):
+            wl = one_body(hinge(th0 + d), faces, Xref=hinge(th0), closed=False)
+            Wb = O.forces(wl, wl.X, O.reference(wl), k)["W"][0, 1]
+            series = d * d / 2 - d ** 4 / 24 + d ** 6 / 720 - d ** 8 / 40320
+            # the fold angle itself carries ~1e-16 of th0 from the rounded
+            # coordinates: an absolute error of about d 1e-16 in W_b / kb
+            assert abs(Wb - kb * series) <= kb * (1e-14 * series + 1e-15 * th0 * d), (th0, d, Wb)
+        for d, want in ((math.pi / 2, 1.0), (math.pi / 3, 0.5)):
+            wl = one_body(hinge(th0 + d), faces, Xref=hinge(th0), closed=False)
+            Wb = O.forces(wl, wl.X, O.reference(wl), k)["W"][0, 1]
+            assert abs(Wb - kb * want) <= 1e-15 * 4, (th0, d, Wb)
+
+
 # ----------------------------------------------------------------------------
 # forces
 # ----------------------------------------------------------------------------
