@@ -123,3 +123,24 @@ def near_bodies(wl, sample, extra_cells=3.0):
         d -= np.round(d)
         near |= set(np.flatnonzero(np.sqrt((d * d).sum(axis=1)) < reach + reach[b]).tolist())
     return sorted(near)
+
+
+def energy_error(Wg, Wo, Vg, Vo, wl, V0, tol):
+    """Worst ratio (<= 1 passes) of the energy differences [B][4] to their bar.
+    W_s, W_b and W_a: elementwise tol.  W_v = kV (V - V0)^2 / (2 V0) depends on
+    the body's volume alone and is conditioned by V / |V - V0|: a volume
+    difference dV between two FP64 summation orders moves it by
+    |dW_v/dV| dV = kV |V - V0| / V0 dV, so its bar is tol W_v plus that
+    propagation of the measured volume difference (V itself is checked at
+    tol on its own)."""
+    Wg, Wo = np.asarray(Wg, np.float64), np.asarray(Wo, np.float64)
+    bar = tol * np.abs(Wo)
+    closed = np.asarray(wl.closed) == 1
+    dV = np.abs(np.asarray(Vg) - np.asarray(Vo))
+    V0 = np.where(closed, np.asarray(V0, np.float64), 1.0)
+    slope = np.asarray(wl.kV) * np.abs(np.asarray(Vo) - V0) / V0
+    bar[:, 3] += np.where(closed, slope * dV * (1 + tol), 0.0)
+    diff = np.abs(Wg - Wo)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(bar > 0, diff / np.where(bar > 0, bar, 1.0), np.where(diff > 0, np.inf, 0.0))
+    return float(r.max()) if r.size else 0.0

@@ -11,8 +11,9 @@ import oracle as O
 from paper_1612_03399_amd import native as N
 from paper_1612_03399_amd import workload as W
 
-from gpu_common import (DEV, TOL, constants, dev, elem_rel, gpu_reference_from_oracle, host,
-                        oracle_reference_as_seen, per_body_rel, rel_inf, step_error)
+from gpu_common import (DEV, TOL, constants, dev, energy_error,
+                        gpu_reference_from_oracle, host, oracle_reference_as_seen, per_body_rel,
+                        rel_inf, step_error)
 
 pytestmark = pytest.mark.gpu
 
@@ -50,15 +51,17 @@ def test_weighted_forces_parity(case, precision):
     plan = N.Plan(wl, wl.grid, precision)
     N.ip_plan_bind_edge_weights(plan, dev(ew))
     Wt = torch.empty(wl.n_bodies, 4, dtype=torch.float64, device=DEV)
+    V = torch.empty(wl.n_bodies, dtype=torch.float64, device=DEV)
     F = N.ip_forces(plan, dev(wl.X), gpu_reference_from_oracle(ref, precision), constants(wl),
-                    W=Wt)
+                    V=V, W=Wt)
     code, flags = N.ip_plan_status(plan)
     assert code == N.IP_OK, flags
     e_f = per_body_rel(host(F).astype(np.float64), want["F"], wl.node_off)
-    e_w = elem_rel(host(Wt), want["W"])
-    say(f"  F {e_f:.2e}  W {e_w:.2e}")
+    e_w = energy_error(host(Wt), want["W"], host(V), want["V"], wl, ref.V0,
+                       1e-12 if precision == "f64" else 1e-6)
+    say(f"  F {e_f:.2e}  W {e_w:.2f} of its bar")
     assert e_f <= TOL[precision]
-    assert e_w <= (1e-12 if precision == "f64" else 1e-6)
+    assert e_w <= 1.0
 
 
 def weighted_step(wl, ref, precision, ew, options=None):
