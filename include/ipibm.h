@@ -220,6 +220,23 @@ ip_status ip_forces(ip_plan *plan, const double *X, const ip_reference *ref,
                     const ip_constants *k, void *F, double *V, double *A, double *W,
                     void *stream);
 
+/* ip_forces for callers that cannot allocate device memory during the call
+ * or hold none of their own beside their inputs and outputs (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results (bitwise) as ip_forces; the
+ * element-slot workspace, and V and A when passed NULL, live in a static
+ * device array of 64 MiB instead of the plan's buffers, so the call allocates
+ * nothing and frees nothing.  The array holds 16 bytes per body (rounded up
+ * to 256) plus 12 (FP64) or 6 (FP32) bytes per edge-slot/face-corner triple,
+ * i.e. 3 (4E + 3F) reals: a plan needing more is refused with IP_ERR_ARG
+ * before any launch (about 60 level-4 icosphere drops in FP64).  Each device
+ * has one array, shared by every call on it and keeping the last call's
+ * contents: calls that overlap on one device (several streams or host
+ * threads) race and must be serialised by the caller. */
+ip_status ip_forces_noalloc(ip_plan *plan, const double *X, const ip_reference *ref,
+                            const ip_constants *k, void *F, double *V, double *A, double *W,
+                            void *stream);
+
 /* Interpolation of the staggered velocity to the nodes with the 3-point
  * regularised delta of Roma, Peskin & Berger (3x3x3 support, the support
  * domain of Section 2.2): U_d(X_l) = sum_k u_d[k] phi phi phi.

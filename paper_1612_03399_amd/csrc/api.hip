@@ -117,6 +117,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
     p->F = F;
     p->prec = prec;
     IP_HIP_CHECK(hipGetDevice(&p->device));
+    IP_TRY(prepare_noalloc_scratch(p->device));
     p->h_node_off.assign(m->node_off, m->node_off + B + 1);
     p->h_edge_off.assign(m->edge_off, m->edge_off + B + 1);
     p->h_face_off.assign(m->face_off, m->face_off + B + 1);
@@ -450,6 +451,16 @@ ip_status ip_forces(ip_plan *plan, const double *X, const ip_reference *ref,
     if (plan->N > 0 && (!X || !F)) return arg_error("X or F is NULL");
     if (!aligned(X, 8) || !aligned(F, plan->real_size())) return arg_error("misaligned X or F");
     return launch_forces(plan, X, ref, k, F, V, A, W, (hipStream_t)stream);
+}
+
+ip_status ip_forces_noalloc(ip_plan *plan, const double *X, const ip_reference *ref,
+                            const ip_constants *k, void *F, double *V, double *A, double *W,
+                            void *stream) {
+    IP_TRY(check_plan(plan));
+    IP_TRY(check_ref_k(plan, ref, k, false));
+    if (plan->N > 0 && (!X || !F)) return arg_error("X or F is NULL");
+    if (!aligned(X, 8) || !aligned(F, plan->real_size())) return arg_error("misaligned X or F");
+    return launch_forces_noalloc(plan, X, ref, k, F, V, A, W, (hipStream_t)stream);
 }
 
 ip_status ibm_interp(ip_plan *plan, const double *X, const void *u, void *U, void *stream) {

@@ -172,6 +172,13 @@ ip_status launch_forces(ip_plan *p, const double *X, const ip_reference *ref,
                         const ip_constants *k, void *F, double *V, double *A, double *W,
                         hipStream_t s);
 ip_status launch_interp(ip_plan *p, const double *X, const void *u, void *U, hipStream_t s);
+// ip_forces with its workspace in the static scratch array (k_forces.hip)
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+ip_status prepare_noalloc_scratch(int device);   // once per device, device current
+size_t noalloc_scratch_need(const ip_plan *p);
+ip_status launch_forces_noalloc(ip_plan *p, const double *X, const ip_reference *ref,
+                                const ip_constants *k, void *F, double *V, double *A,
+                                double *W, hipStream_t s);
 ip_status launch_spread(ip_plan *p, const double *X, const void *F, void *f, hipStream_t s);
 // MLS transfer at the triangle centroids (k_mls.hip)
 ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double alpha, void *U,

@@ -2,6 +2,8 @@
 // per-body geometry reductions, per-edge spring + bending hinge, per-face area +
 // volume-gradient, and the scatter-free gather of element results into nodes.
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "elements.h"
 #include "ipibm_internal.h"
@@ -229,13 +231,11 @@ __global__ __launch_bounds__(kGeomThreads) void k_energy(
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// slots: element-slot workspace, [(4E + 3F)][3] R; Vb, Ab: [B] doubles
 template <typename R>
 ip_status forces_impl(ip_plan *p, const double *X, const ip_reference *ref,
-                      const ip_constants *k, void *Fv, double *V, double *A, double *W,
-                      hipStream_t s) {
-    R *slots = (R *)p->slots;
-    double *Vb = V ? V : p->Vbuf;
-    double *Ab = A ? A : p->Abuf;
+                      const ip_constants *k, void *Fv, double *Vb, double *Ab, double *W,
+                      R *slots, hipStream_t s) {
     if (p->B > 0)
         hipLaunchKernelGGL(k_geometry<R>, dim3(p->B), dim3(kGeomThreads), 0, s, X, p->faces,
                            p->node_off, p->face_off, Vb, Ab, (const int32_t *)nullptr);
@@ -335,6 +335,79 @@ ip_status launch_reference(ip_plan *p, const double *Xref, void *l0, void *cs0, 
 ip_status launch_forces(ip_plan *p, const double *X, const ip_reference *ref,
                         const ip_constants *k, void *F, double *V, double *A, double *W,
                         hipStream_t s) {
-    return p->prec == IP_F64 ? forces_impl<double>(p, X, ref, k, F, V, A, W, s)
-                             : forces_impl<float>(p, X, ref, k, F, V, A, W, s);
+    double *Vb = V ? V : p->Vbuf;
+    double *Ab = A ? A : p->Abuf;
+    return p->prec == IP_F64
+               ? forces_impl<double>(p, X, ref, k, F, Vb, Ab, W, (double *)p->slots, s)
+               : forces_impl<float>(p, X, ref, k, F, Vb, Ab, W, (float *)p->slots, s);
+}
+
+// ----------------------------------------------------------------------------
+// ip_forces_noalloc: the same kernels with their workspace (the element slots,
+// and V, A when the caller passes none) in a static device array instead of
+// the plan's allocations, for callers that cannot allocate.  Each device holds
+// its own copy of the array for the life of the process; its address on a
+// device is looked up once, at the first plan creation on that device, and
+// only that address reaches kernels.  Every slot, V and A entry is written
+// before it is read, so nothing needs clearing between calls.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+}  // namespace
+
+ip_status prepare_noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        ipibm_set_error("device id " + std::to_string(device) + " beyond the scratch table");
+        return IP_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return IP_OK;
+    void *ptr = nullptr;
+    IP_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+        ipibm_set_error("hipGetSymbolAddress returned no address for the static scratch");
+        return IP_ERR_HIP;
+    }
+    g_scratch_ptr[device] = ptr;
+    return IP_OK;
+}
+
+size_t noalloc_scratch_need(const ip_plan *p) {
+    return align_up((size_t)p->B * 2 * sizeof(double), 256) +
+           (size_t)(4 * p->E + 3 * p->F) * 3 * p->real_size();
+}
+
+ip_status launch_forces_noalloc(ip_plan *p, const double *X, const ip_reference *ref,
+                                const ip_constants *k, void *F, double *V, double *A,
+                                double *W, hipStream_t s) {
+    const size_t need = noalloc_scratch_need(p);
+    if (need > (size_t)kNoAllocScratchBytes) {
+        ipibm_set_error("ip_forces_noalloc: the plan needs " + std::to_string(need) +
+                        " bytes of scratch, more than the " +
+                        std::to_string((size_t)kNoAllocScratchBytes) +
+                        " bytes of the static array (use ip_forces)");
+        return IP_ERR_ARG;
+    }
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (p->device >= 0 && p->device < kMaxDevices) base = g_scratch_ptr[p->device];
+    }
+    if (!base) {
+        ipibm_set_error("ip_forces_noalloc: no static scratch address for device " +
+                        std::to_string(p->device));
+        return IP_ERR_UNSUPPORTED;
+    }
+    double *Vb = V ? V : (double *)base;
+    double *Ab = A ? A : (double *)base + p->B;
+    void *slots = (unsigned char *)base + align_up((size_t)p->B * 2 * sizeof(double), 256);
+    return p->prec == IP_F64
+               ? forces_impl<double>(p, X, ref, k, F, Vb, Ab, W, (double *)slots, s)
+               : forces_impl<float>(p, X, ref, k, F, Vb, Ab, W, (float *)slots, s);
 }

@@ -71,6 +71,8 @@ def _load():
         "ip_reference_from": [vp, vp, vp, vp, vp, vp, vp],
         "ip_forces": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp, vp, vp,
                       vp],
+        "ip_forces_noalloc": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp,
+                              vp, vp, vp],
         "ibm_interp": [vp, vp, vp, vp, vp],
         "ibm_spread": [vp, vp, vp, vp, vp],
         "ip_step": [vp, vp, C.POINTER(ip_reference), C.POINTER(ip_constants), vp, vp, d, vp,
@@ -244,6 +246,16 @@ def ip_forces(plan: Plan, X, ref: Reference, k: Constants, F=None, V=None, A=Non
     r, kk = _refp(ref), k.struct()
     _check(LIB.ip_forces(plan.handle, _ptr(X), r, C.byref(kk), _ptr(F), _ptr(V),
                          _ptr(A), _ptr(W), _stream(stream)))
+    return F
+
+
+def ip_forces_noalloc(plan: Plan, X, ref: Reference, k: Constants, F, V=None, A=None, W=None,
+                      stream=None):
+    """ip_forces with its workspace in the library's static scratch: F (and
+    V, A, W when wanted) must be given, so nothing is allocated here either."""
+    r, kk = _refp(ref), k.struct()
+    _check(LIB.ip_forces_noalloc(plan.handle, _ptr(X), r, C.byref(kk), _ptr(F), _ptr(V),
+                                 _ptr(A), _ptr(W), _stream(stream)))
     return F
 
 
