@@ -6,8 +6,10 @@ the accumulation into nodes, interpolation of the staggered velocity,
 spreading of the nodal forces and the explicit update.  The default workload
 is 1000 level-4 icosphere drops (2 562 000 nodes) on a 256^3 MAC grid in FP64,
 synthetic seeded inputs resident in HBM before the timed region.  With the
-fused path the step is one kernel launch (k_step_fused), so the events around
-the timed steps measure that kernel on the stream it is launched on.
+fused path the step is one kernel launch (k_step_fused).  The headline times
+a hipGraph of K captured steps, replayed once between HIP events on the
+stream the kernels run on (after W eager warm-up steps and one untimed
+replay); the same K steps launched eagerly are reported beside it.
 
 Prints ONE JSON line.
 """
@@ -67,6 +69,54 @@ def touched_points(X, grid, offsets=MAC_OFFSETS):
     return total
 
 
+def touched_points_device(X, grid, offsets=MAC_OFFSETS, device="cuda"):
+    """touched_points() with torch on `device` (for batches of millions of
+    nodes): a boolean mask per lattice, set at every support point."""
+    import torch
+    Xt = torch.as_tensor(np.ascontiguousarray(X, np.float64), device=device)
+    n = torch.tensor([grid.nx, grid.ny, grid.nz], dtype=torch.int64, device=device)
+    total = 0
+    for off in offsets:
+        c = torch.floor(Xt / grid.h - torch.tensor(off, dtype=torch.float64, device=device)
+                        + 0.5).to(torch.int64)
+        mask = torch.zeros(grid.nx * grid.ny * grid.nz, dtype=torch.bool, device=device)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    i = torch.remainder(c + torch.tensor([dx, dy, dz], device=device), n)
+                    mask[(i[:, 2] * n[1] + i[:, 1]) * n[0] + i[:, 0]] = True
+        total += int(mask.sum().item())
+        del mask, c
+    return total
+
+
+def roofline_block(bytes_per_launch, ms, kernel, extra=None):
+    """The roofline object of one leg: algorithmic bytes of one launch over its
+    measured duration, against the HBM peak."""
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+           "algorithmic_bytes_per_launch": int(bytes_per_launch), "ms_per_launch": ms}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def reverse_bytes(wl, touched):
+    """Bytes one reverse step (k_step_vjp_fused, FP64) must move: X read,
+    the incoming adjoint read and the outgoing one written, the pinned mask,
+    the packed element records, per-body arrays with the constants' gradients,
+    and over the touched grid values u read and the velocity gradient read,
+    added to and written."""
+    N, E, F, B = wl.n_nodes, wl.n_edges, wl.n_faces, wl.n_bodies
+    nodes = N * (8 * 3 * 3 + 1)
+    edges = E * 32
+    faces = F * 16
+    bodies = B * (8 * 8 + 1 + 8 * 3 + 8 * 4)
+    grid = touched * 8 * 3
+    return nodes + edges + faces + bodies + grid
+
+
 def algorithmic_bytes(wl, touched, real_bytes):
     """Bytes one step must move at minimum, in the layout the step reads with a
     bound reference: X read + write (FP64), pinned mask, the packed element
@@ -114,25 +164,128 @@ def load_valu(workload, dtype, launch, ms):
             "frac": per_s / VALU_PEAK_WAVE_INSTS, "source": os.path.relpath(path, ROOT)}
 
 
-def cpu_baseline(wl, u, budget_s=20.0):
-    """The FP64 oracle (single thread, as it stands) on a bounded sample of the
-    same workload: whole-batch steps until ~budget_s/2 of CPU work."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_POOL = {}
+
+
+def _oracle_worker(w, ids, shm_name, shape, barrier, go, done):
+    """One process of the parallel oracle: steps its bodies of the batch
+    (the oracle unchanged) into its own force field, then adds slab w of
+    every process's field into field 0."""
+    from multiprocessing import shared_memory
+    import oracle as O
+    from paper_1612_03399_amd import workload as W
+    wl, u = _POOL["wl"], _POOL["u"]
+    P = len(_POOL["parts"])
+    shm = shared_memory.SharedMemory(name=shm_name)
+    fs = np.ndarray((P,) + shape, dtype=np.float64, buffer=shm.buf)
+    sub = W.subset(wl, ids)
+    ref = O.reference(sub)
+    X = sub.X.copy()
+    fs[w][...] = 0.0
+    barrier.wait(timeout=600)           # set-up done
+    go.wait()
+    O.step(sub, X, ref, u, wl.dt, fs[w])
+    barrier.wait(timeout=600)           # every field complete
+    nz = shape[1]
+    z0, z1 = w * nz // P, (w + 1) * nz // P
+    for q in range(1, P):
+        fs[0][:, z0:z1] += fs[q][:, z0:z1]
+    barrier.wait(timeout=600)
+    del fs
+    shm.close()
+    done.set()
+
+
+def cpu_baseline(wl, u, log, single_budget_s=12.0):
+    """The FP64 oracle as it stands, timed on the host: one thread on whole
+    steps of the batch, and every core available to this process (at most 16)
+    with the bodies split into contiguous ranges, one process per range
+    calling the unchanged oracle on its bodies, then summing the per-process
+    force fields slab by slab (part of the timed step)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
     import oracle as O
     ref = O.reference(wl)
-    f = np.zeros_like(u)
+    f1 = np.zeros_like(u)            # the first step's field, for the parallel run's check
+    f2 = np.zeros_like(u)
     X = wl.X.copy()
     steps = 0
     t0 = time.perf_counter()
     while True:
-        X = O.step(wl, X, ref, u, wl.dt, f)["X"]
+        X = O.step(wl, X, ref, u, wl.dt, f1 if steps == 0 else f2)["X"]
         steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s / 2 or steps >= 3:
+        el1 = time.perf_counter() - t0
+        if el1 > single_budget_s / 2 or steps >= 3:
             break
-    return {"value": wl.n_nodes * steps / el, "unit": "node-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} full step(s) of the {wl.n_bodies}-body batch "
-                      f"({wl.n_nodes} nodes), {el:.1f} s"}
+    single = wl.n_nodes * steps / el1
+    log(f"cpu baseline, 1 thread: {steps} step(s) in {el1:.1f} s = {single:.3e} node-steps/s")
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16, wl.n_bodies))
+    out = {"value": single, "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} full step(s) of the {wl.n_bodies}-body batch "
+                     f"({wl.n_nodes} nodes), {el1:.1f} s on 1 thread",
+           "single_thread_value": single, "cpu_model": cpu_model()}
+    if cores < 2:
+        return out
+    P = cores
+    sizes = np.diff(np.asarray(wl.node_off))
+    cut = np.searchsorted(np.cumsum(sizes), np.arange(1, P) * sizes.sum() / P)
+    parts = [p.tolist() for p in np.split(np.arange(wl.n_bodies), cut) if len(p)]
+    P = len(parts)
+    shape = u.shape
+    shm = shared_memory.SharedMemory(create=True, size=P * u.nbytes)
+    try:
+        _POOL.update(wl=wl, u=u, parts=parts)
+        ctx = mp.get_context("fork")
+        barrier, go = ctx.Barrier(P + 1), ctx.Event()
+        dones = [ctx.Event() for _ in range(P)]
+        procs = [ctx.Process(target=_oracle_worker, args=(w, parts[w], shm.name, shape, barrier,
+                                                          go, dones[w]))
+                 for w in range(P)]
+        for pr in procs:
+            pr.start()
+        try:
+            barrier.wait(timeout=600)   # every process has its bodies and reference
+            t0 = time.perf_counter()
+            go.set()
+            barrier.wait(timeout=600)   # fields done
+            barrier.wait(timeout=600)   # fields summed
+            elp = time.perf_counter() - t0
+        except Exception as e:          # a process failed: report the one-thread figure
+            for pr in procs:
+                pr.terminate()
+            for pr in procs:
+                pr.join()
+            log(f"cpu baseline: parallel oracle failed ({type(e).__name__}); 1 thread only")
+            return out
+        for pr in procs:
+            pr.join()
+        fs = np.ndarray((P,) + shape, dtype=np.float64, buffer=shm.buf)
+        check = float(np.abs(fs[0] - f1).max() / max(np.abs(f1).max(), 1e-300))
+        del fs
+    finally:
+        _POOL.clear()
+        shm.close()
+        shm.unlink()
+    par = wl.n_nodes / elp
+    log(f"cpu baseline, {P} processes: 1 step in {elp:.2f} s = {par:.3e} node-steps/s")
+    out.update({"value": par, "cores": P,
+                "sample": f"1 full step of the {wl.n_bodies}-body batch ({wl.n_nodes} nodes) "
+                          f"on {P} processes (bodies split in {P} ranges, force fields summed "
+                          f"by slab), {elp:.2f} s; and {steps} step(s) on 1 thread, {el1:.1f} s",
+                "parallel_value": par, "parallel_seconds": elp,
+                "parallel_field_rel_diff": check})
+    return out
 
 
 def time_steps(N, plan, X, ref, k, u, f, dt, V, A, steps, warmup, stream, torch):
@@ -146,6 +299,29 @@ def time_steps(N, plan, X, ref, k, u, f, dt, V, A, steps, warmup, stream, torch)
         N.ip_step(plan, X, ref, k, u, f, dt, V, A, stream)
     e1.record(stream)
     torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_graph(N, plan, X, ref, k, u, f, dt, V, A, steps, warmup, torch):
+    """W eager warm-up steps, a hipGraph of `steps` captured steps replayed
+    once untimed, then once between HIP events on the replay stream."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        N.ip_step(plan, X, ref, k, u, f, dt, V, A, stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(steps):
+            N.ip_step(plan, X, ref, k, u, f, dt, V, A, torch.cuda.current_stream())
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del g
     return e0.elapsed_time(e1) / steps
 
 
@@ -183,11 +359,51 @@ def backward_leg(N, W, bodies, dev, torch, log, steps=10, reps=3):
             bwd.append(e[1].elapsed_time(e[2]))
     f, b = float(np.median(fwd)), float(np.median(bwd))
     log(f"backward leg: fwd {f:.3f} ms, bwd {b:.3f} ms for {steps} steps (ratio {b / f:.2f})")
+    # the reverse-step kernel alone: one ip_step_vjp per step, against one
+    # forward ip_step, each timed over `kreps` back-to-back calls
+    k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
+    X = X0.clone()
+    lam = torch.randn(X.shape, dtype=torch.float64, device=dev, generator=torch.Generator(
+        device=dev).manual_seed(1004))
+    lam2 = torch.empty_like(lam)
+    gk = torch.zeros(4, wl.n_bodies, dtype=torch.float64, device=dev)
+    gu = torch.zeros_like(u)
+    stream = torch.cuda.current_stream()
+    kreps = 20
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(kreps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / kreps
+
+    t_rev = timed(lambda: N.ip_step_vjp(plan, X, ref, k, u, wl.dt, lam, lam2, gk, gu,
+                                        stream=stream))
+    f_grid = torch.zeros_like(u)
+    Xf = X0.clone()
+    t_fwd = timed(lambda: N.ip_step(plan, Xf, ref, k, u, f_grid, wl.dt, stream=stream))
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags} in the backward leg")
-    return {"diff_workload": wl.name, "diff_steps": steps, "diff_fwd_ms": f, "diff_bwd_ms": b,
-            "diff_bwd_over_fwd": b / f, "diff_loss": float(loss.item())}
+    touched = touched_points_device(wl.X, wl.grid, device=dev)
+    rb = reverse_bytes(wl, touched)
+    log(f"reverse step kernel: {t_rev:.4f} ms against {t_fwd:.4f} ms forward "
+        f"({t_rev / t_fwd:.2f}x), {rb / (t_rev * 1e-3) / (HBM_PEAK_GBS * 1e9):.1%} of HBM")
+    out = {"diff_workload": wl.name, "diff_steps": steps, "diff_fwd_ms": f, "diff_bwd_ms": b,
+           "diff_bwd_over_fwd": b / f, "diff_loss": float(loss.item()),
+           "reverse_step_ms": t_rev, "forward_step_ms": t_fwd,
+           "reverse_over_forward_step": t_rev / t_fwd,
+           "reverse_roofline": roofline_block(rb, t_rev, "k_step_vjp_fused<768, false>",
+                                              {"touched_grid_points": touched})}
+    del plan, X, Xf, lam, lam2, gk, gu, f_grid, u
+    torch.cuda.empty_cache()
+    return out
 
 
 def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
@@ -208,8 +424,8 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
     X = torch.as_tensor(wl.X).to(dev)
     Xref = torch.as_tensor(wl.Xref).to(dev)
     from paper_1612_03399_amd import autotune as AT
-    opts, tuned = AT.autotune(wl, wl.grid, "f32", X, None, k, u, wl.dt,
-                              candidates=AT.UNEVEN_CANDIDATES, Xref=Xref)
+    opts, tuned, tinfo = AT.autotune(wl, wl.grid, "f32", X, None, k, u, wl.dt, Xref=Xref)
+    log(f"  uneven autotune: cache {tinfo['cache']} ({tinfo['seconds']:.1f} s)")
     for r in tuned:
         log(f"  uneven options {r['options']}: {r['ms']:.3f} ms ({r['units']} units, "
             f"{r['threads']} threads, tile {r['tile_bytes']} B)")
@@ -245,11 +461,21 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags} in the uneven leg")
+    touched = touched_points_device(wl.X, wl.grid, device=dev)
+    ub = algorithmic_bytes(wl, touched, 4)
     out = {"uneven_workload": wl.name, "uneven_nodes": wl.n_nodes, "uneven_options": opts,
-           "uneven_autotune": [{"options": r["options"], "ms": r["ms"]} for r in tuned],
+           "uneven_autotune": [{"options": r["options"], "ms": r["ms"], "stage": r["stage"]}
+                               for r in tuned],
+           "uneven_autotune_cache": tinfo["cache"],
            "uneven_units": plan.n_units, "uneven_patched_bodies": plan.patched_bodies,
            "uneven_batched_ms": batched, "uneven_graph_ms": graph,
-           "uneven_node_steps_per_s": wl.n_nodes / (graph * 1e-3)}
+           "uneven_node_steps_per_s": wl.n_nodes / (graph * 1e-3),
+           "uneven_roofline": roofline_block(
+               ub, graph, "k_step_fused<float, %d, false> + geometry and commit passes"
+               % plan.step_threads, {"touched_grid_points": touched,
+                                     "bytes_per_node": ub / wl.n_nodes})}
+    log(f"uneven: {ub / 1e9:.3f} GB algorithmic per step, "
+        f"{out['uneven_roofline']['frac']:.1%} of HBM at the graph replay's time")
     del gr, plan
     # per-body launches on a sample, against the batched step of the same bodies
     ids = np.sort(np.random.default_rng(7).choice(wl.n_bodies, sample, replace=False))
@@ -413,21 +639,29 @@ def main():
     k = N.Constants.from_arrays(wl.ks, wl.kb, wl.kA, wl.kV, wl.mass, dev)
     X0 = torch.as_tensor(wl.X).to(dev)
 
-    # launch shape: autotuned on this batch (untimed set-up) unless given
-    tuning = None
+    # launch shape: autotuned on this batch (untimed set-up) unless given; the
+    # search is cached, so a second call is a lookup (reported)
+    tuning, tune_info = None, None
     if args.options is not None:
         options = json.loads(args.options)
     else:
         rdt = N.real_dtype(args.precision)
         probe = N.Plan(wl, wl.grid, args.precision)
         ref0 = N.ip_reference_from(probe, torch.as_tensor(wl.Xref).to(dev))
-        options, tuning = AT.autotune(wl, wl.grid, args.precision, X0, ref0, k,
-                                      torch.as_tensor(u_host).to(dev, rdt), wl.dt)
+        ut = torch.as_tensor(u_host).to(dev, rdt)
+        options, tuning, tune_info = AT.autotune(wl, wl.grid, args.precision, X0, ref0, k, ut,
+                                                 wl.dt)
+        again, _, info2 = AT.autotune(wl, wl.grid, args.precision, X0, ref0, k, ut, wl.dt)
+        assert again == options
+        tune_info = {"first": tune_info, "second": info2}
         probe.close()
+        del ut
         for r in tuning:
             log(f"  options {r['options']}: {r['ms']:.4f} ms ({r['units']} units, "
                 f"{r['threads']} threads, tile {r['tile_bytes']} B)")
-        log(f"autotuned options: {options}")
+        log(f"autotuned options: {options} (cache {tune_info['first']['cache']} in "
+            f"{tune_info['first']['seconds']:.1f} s, then {tune_info['second']['cache']} in "
+            f"{tune_info['second']['seconds'] * 1e3:.1f} ms)")
 
     def setup(precision):
         rdt = N.real_dtype(precision)
@@ -442,15 +676,18 @@ def main():
         return plan, None, k, X, u, f, V, A
 
     plan, ref, k, X, u, f, V, A = setup(args.precision)
-    ms = time_steps(N, plan, X, ref, k, u, f, wl.dt, V, A, args.steps, args.warmup, stream, torch)
+    # the same K steps launched eagerly, then as a replayed hipGraph (headline)
+    eager_ms = time_steps(N, plan, X, ref, k, u, f, wl.dt, V, A, args.steps, args.warmup,
+                          stream, torch)
+    ms = time_graph(N, plan, X, ref, k, u, f, wl.dt, V, A, args.steps, args.warmup, torch)
     code, flags = N.ip_plan_status(plan)
     if code != N.IP_OK:
         raise SystemExit(f"device status {code} flags {flags}")
-    log(f"timed {args.steps} steps: {ms:.4f} ms/step (fused path: {plan.fused}, "
-        f"{plan.n_units} units, {plan.step_threads} threads)")
+    log(f"timed {args.steps} steps: graph replay {ms:.4f} ms/step, eager {eager_ms:.4f} ms/step "
+        f"(fused path: {plan.fused}, {plan.n_units} units, {plan.step_threads} threads)")
 
     real_bytes = 8 if args.precision == "f64" else 4
-    touched = touched_points(wl.X, wl.grid)
+    touched = touched_points_device(wl.X, wl.grid, device=dev)
     bytes_step = algorithmic_bytes(wl, touched, real_bytes)
     gbs = bytes_step / (ms * 1e-3) / 1e9
     value = wl.n_nodes / (ms * 1e-3)
@@ -471,7 +708,8 @@ def main():
                    "edges": wl.n_edges, "faces": wl.n_faces,
                    "grid": [wl.grid.nx, wl.grid.ny, wl.grid.nz], "dt": wl.dt,
                    "launch_options": options, "work_units": plan.n_units,
-                   "threads": plan.step_threads},
+                   "threads": plan.step_threads, "timing": "hipGraph replay of the timed steps",
+                   "eager_ms_per_step": eager_ms},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel,
@@ -484,8 +722,10 @@ def main():
                      "valu_issue": load_valu(wl.name, args.precision, launch, ms)},
     }
     if tuning is not None:
-        out["autotune"] = [{"options": r["options"], "ms": r["ms"], "units": r["units"],
-                            "threads": r["threads"]} for r in tuning]
+        out["autotune"] = {"choice": options, "cache": tune_info,
+                           "searched": [{"options": r["options"], "ms": r["ms"],
+                                         "stage": r["stage"], "units": r["units"],
+                                         "threads": r["threads"]} for r in tuning]}
     del plan, X, u, f
     torch.cuda.empty_cache()
 
@@ -495,36 +735,23 @@ def main():
     if "other" in legs:
         other = "f32" if args.precision == "f64" else "f64"
         plan2, ref2, k2, X2, u2, f2, V2, A2 = setup(other)
-        ms2 = time_steps(N, plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, args.steps,
-                         args.warmup, stream, torch)
+        ms2e = time_steps(N, plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, args.steps,
+                          args.warmup, stream, torch)
+        ms2 = time_graph(N, plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, args.steps,
+                         args.warmup, torch)
+        code, flags = N.ip_plan_status(plan2)
+        if code != N.IP_OK:
+            raise SystemExit(f"device status {code} flags {flags} in the {other} leg")
+        b2 = algorithmic_bytes(wl, touched, 8 if other == "f64" else 4)
         extras[f"{other}_ms_per_step"] = ms2
+        extras[f"{other}_eager_ms_per_step"] = ms2e
         extras[f"{other}_node_steps_per_s"] = wl.n_nodes / (ms2 * 1e-3)
-        log(f"{other}: {ms2:.4f} ms/step")
-        # the same steps captured once in a hipGraph and replayed
-        g = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            N.ip_step(plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2, s)
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(g):
-            for _ in range(10):
-                N.ip_step(plan2, X2, ref2, k2, u2, f2, wl.dt, V2, A2,
-                          torch.cuda.current_stream())
-        g.replay()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = max(1, args.steps // 10)
-        e0.record()
-        for _ in range(reps):
-            g.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        extras[f"{other}_graph_ms_per_step"] = e0.elapsed_time(e1) / (10 * reps)
-        log(f"{other} graph replay: {extras[f'{other}_graph_ms_per_step']:.4f} ms/step")
-        del g, plan2, X2, u2, f2
+        extras[f"{other}_roofline"] = roofline_block(
+            b2, ms2, f"k_step_fused<{'double' if other == 'f64' else 'float'}, "
+                     f"{plan2.step_threads}, false>", {"bytes_per_node": b2 / wl.n_nodes})
+        log(f"{other}: graph replay {ms2:.4f} ms/step, eager {ms2e:.4f} ms/step, "
+            f"{extras[f'{other}_roofline']['frac']:.1%} of HBM")
+        del plan2, X2, u2, f2
         torch.cuda.empty_cache()
     if "weights" in legs:
         # per-edge weights on ks and kb bound to a plan of the same shape: the
@@ -557,7 +784,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, u_host)
+        out["cpu_baseline"] = cpu_baseline(wl, u_host, log)
     print(json.dumps(out), flush=True)
 
 

@@ -127,16 +127,24 @@ typedef struct {
  *   tile_bytes  cap on the LDS tile region of a workgroup (default: all LDS
  *               left once the largest unit's arrays are placed; at least
  *               4096);
- *   threads     threads per workgroup of the fused kernel: 768 (default) or
- *               384, with units of at most 4 x threads nodes.  At 384
- *               threads, small units and a capped tile let two workgroups
- *               share a compute unit.
+ *   threads     threads per workgroup of the fused kernel, with units of at
+ *               most 4 x threads nodes: 768, 384 or 256 for every unit; by
+ *               default units above 1536 nodes run on 768 threads and the
+ *               others on 384;
+ *   wg_per_cu   workgroups per compute unit the tile of the smaller-unit
+ *               launch (the only one when `threads` is set) is sized for:
+ *               1 to 4 (default 2 for the 384-thread launch of the default
+ *               split, else 1).  The LDS left per workgroup, once the
+ *               largest unit's arrays are placed, is the tile; a unit whose
+ *               cell box does not fit it spreads and interpolates directly
+ *               against the grid.
  * The choice changes the speed, not the results beyond summation order. */
 typedef struct {
     int32_t unit_nodes;
     int32_t patch_owned;
     int32_t tile_bytes;
     int32_t threads;
+    int32_t wg_per_cu;
 } ip_plan_options;
 
 /* Build a plan: validates and copies the mesh, builds the node gather lists

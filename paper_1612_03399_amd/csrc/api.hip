@@ -175,7 +175,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
     // threads: 0 = large units on 768-thread workgroups and units of at most
     // 384 x 4 nodes on 384-thread ones (two per compute unit); 768 or 384 =
     // every unit on that size
-    const int big = opt.threads == 384 ? 384 : 768;
+    const int big = opt.threads > 0 ? opt.threads : 768;
     const int unit_max = big * kStepNodesPerThread;
     const int unit_nodes = opt.unit_nodes > 0 ? std::min(opt.unit_nodes, unit_max) : unit_max;
     const int unit_faces = big * kStepFacesPerThread;
@@ -211,7 +211,12 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
             sc.nmax = 1;
             for (int w = sc.unit_begin; w < sc.unit_end; ++w)
                 sc.nmax = std::max(sc.nmax, wu.units[w].n_nodes);
-            long long t = c == 1 ? tile_for(sc.nmax, 2) : -1;
+            // the last launch (the smaller units, or the only one) is sized
+            // for wg_per_cu workgroups per compute unit when that is set, the
+            // 384-thread launch of the default split for two
+            const bool last = bounds[c + 1] == W;
+            const int share = last && opt.wg_per_cu > 0 ? opt.wg_per_cu : (c == 1 ? 2 : 1);
+            long long t = share > 1 ? tile_for(sc.nmax, share) : -1;
             if (t < 4096) t = tile_for(sc.nmax, 1);
             ok = ok && t >= 4096;
             sc.tile_bytes = (int)std::max<long long>(t, 0);
@@ -325,7 +330,9 @@ ip_status ip_plan_create_ex(ip_plan **plan, const ip_mesh *mesh, const ip_grid *
         if (opt.unit_nodes < 0 || opt.patch_owned < 0 || opt.tile_bytes < 0 ||
             (opt.patch_owned > 0 && opt.patch_owned < 16) ||
             (opt.tile_bytes > 0 && opt.tile_bytes < 4096) ||
-            (opt.threads != 0 && opt.threads != 384 && opt.threads != 768))
+            (opt.threads != 0 && opt.threads != 256 && opt.threads != 384 &&
+             opt.threads != 768) ||
+            opt.wg_per_cu < 0 || opt.wg_per_cu > 4)
             return arg_error("invalid plan options");
     }
     ip_plan *p = new ip_plan();

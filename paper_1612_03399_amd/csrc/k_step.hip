@@ -52,8 +52,10 @@ struct StepArgs {
 };
 
 // EW: the edges carry per-edge weights on ks and kb (record order).
+// NT = 256 workgroups are meant to share a compute unit three at a time,
+// which caps their registers at 168.
 template <typename R, int NT, bool EW>
-__global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
+__global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int ired[6 * (NT / 64)];
@@ -254,14 +256,14 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
             lds_barrier();
             if (pf_ok && d < 2) pf.load(ud + a.field, tg);
         }
-        for (int p = tid; p < N; p += NT) {
-            R wx[3], wy[3], wz[3];
-            const double xd = xs[3 * p + d];
-            const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
-            const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
-            const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
-            R acc = 0;
-            if (use_tile) {
+        if (use_tile) {
+            for (int p = tid; p < N; p += NT) {
+                R wx[3], wy[3], wz[3];
+                const double xd = xs[3 * p + d];
+                const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
+                const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
+                const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
+                R acc = 0;
                 const int lx = cx - kmin[0], ly = cy - kmin[1], lz = cz - kmin[2];
                 if (lx < 0 || ly < 0 || lz < 0 || lx + 2 >= Tx || ly + 2 >= Ty || lz + 2 >= Tz) {
                     bad = true;
@@ -274,21 +276,53 @@ __global__ __launch_bounds__(NT) void k_step_fused(StepArgs a) {
                             acc += wz[z] * wy[y] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
                         }
                 }
-            } else {
-#pragma unroll
-                for (int z = 0; z < 3; ++z)
-#pragma unroll
-                    for (int y = 0; y < 3; ++y) {
-                        const R *row = ud + wrapi(cz - 1 + z, a.nz) * a.plane +
-                                       (int64_t)wrapi(cy - 1 + y, a.ny) * a.nx;
-                        acc += wz[z] * wy[y] *
-                               (wx[0] * row[wrapi(cx - 1, a.nx)] + wx[1] * row[wrapi(cx, a.nx)] +
-                                wx[2] * row[wrapi(cx + 1, a.nx)]);
-                    }
+                const double fd = Fs[3 * p + d];
+                if (!isfinite(fd) || !isfinite((double)acc)) atomicOr(a.status, IP_STATUS_NONFINITE);
+                Fs[3 * p + d] = xd + a.dt * (double)acc + cm * (double)(R)fd;
             }
-            const double fd = Fs[3 * p + d];
-            if (!isfinite(fd) || !isfinite((double)acc)) atomicOr(a.status, IP_STATUS_NONFINITE);
-            Fs[3 * p + d] = xd + a.dt * (double)acc + cm * (double)(R)fd;
+        } else {
+            // directly from the grid, three lanes per node (21 nodes per
+            // wave): lane j reads column x = j of the stencil's nine rows,
+            // so the three reads of a row share a cache line, and the node's
+            // value is the sum over its three lanes
+            const int lane = tid & 63, j = lane % 3;
+            for (int pb = (tid >> 6) * 21; pb < N; pb += (NT / 64) * 21) {
+                const int p = pb + lane / 3;
+                const bool act = lane < 63 && p < N;
+                R acc = 0;
+                if (act) {
+                    R wx[3], wy[3], wz[3];
+                    const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
+                    const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
+                    const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
+                    const R *col = ud + wrapi(cx - 1 + j, a.nx);
+                    int64_t iy[3], iz[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        iy[k] = (int64_t)wrapi(cy - 1 + k, a.ny) * a.nx;
+                        iz[k] = (int64_t)wrapi(cz - 1 + k, a.nz) * a.plane;
+                    }
+                    R v[3][3];
+#pragma unroll
+                    for (int z = 0; z < 3; ++z)
+#pragma unroll
+                        for (int y = 0; y < 3; ++y) v[z][y] = col[iz[z] + iy[y]];
+#pragma unroll
+                    for (int z = 0; z < 3; ++z)
+#pragma unroll
+                        for (int y = 0; y < 3; ++y) acc += wz[z] * wy[y] * v[z][y];
+                    acc *= j == 0 ? wx[0] : (j == 1 ? wx[1] : wx[2]);
+                }
+                // every lane of the wave takes part in the exchange
+                const R s1 = __shfl_down(acc, 1, 64), s2 = __shfl_down(acc, 2, 64);
+                if (act && j == 0) {
+                    const R tot = acc + s1 + s2;
+                    const double xd = xs[3 * p + d];
+                    const double fd = Fs[3 * p + d];
+                    if (!isfinite(fd) || !isfinite((double)tot)) atomicOr(a.status, IP_STATUS_NONFINITE);
+                    Fs[3 * p + d] = xd + a.dt * (double)tot + cm * (double)(R)fd;
+                }
+            }
         }
         if (use_tile) lds_barrier();
     }
@@ -410,8 +444,9 @@ size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
 
 template <typename R, bool EW>
 const void *step_kernel(int threads) {
-    return threads == 384 ? (const void *)k_step_fused<R, 384, EW>
-                          : (const void *)k_step_fused<R, 768, EW>;
+    return threads == 256   ? (const void *)k_step_fused<R, 256, EW>
+           : threads == 384 ? (const void *)k_step_fused<R, 384, EW>
+                            : (const void *)k_step_fused<R, 768, EW>;
 }
 
 ip_status prepare_step_fused(ip_plan *p) {
@@ -487,12 +522,16 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
         const size_t lds = step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
         const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
         if (p->prec == IP_F64) {
-            if (sc.threads == 384)
+            if (sc.threads == 256)
+                launch_step_variant<double, 256>(grid, block, lds, s, a);
+            else if (sc.threads == 384)
                 launch_step_variant<double, 384>(grid, block, lds, s, a);
             else
                 launch_step_variant<double, 768>(grid, block, lds, s, a);
         } else {
-            if (sc.threads == 384)
+            if (sc.threads == 256)
+                launch_step_variant<float, 256>(grid, block, lds, s, a);
+            else if (sc.threads == 384)
                 launch_step_variant<float, 384>(grid, block, lds, s, a);
             else
                 launch_step_variant<float, 768>(grid, block, lds, s, a);

@@ -650,21 +650,31 @@ __device__ void spread_to_grid(const double *xs, const double *vals, int N, cons
             }
             lds_barrier();
         } else {
-            for (int p = tid; p < N; p += NT) {
-                R wx[3], wy[3], wz[3];
-                const int cx = delta3<R>(xs[3 * p] * inv_h - mac_off(d, 0), wx);
-                const int cy = delta3<R>(xs[3 * p + 1] * inv_h - mac_off(d, 1), wy);
-                const int cz = delta3<R>(xs[3 * p + 2] * inv_h - mac_off(d, 2), wz);
-                const R fv = (R)(vals[3 * p + d] * inv_h3);
-                for (int z = 0; z < 3; ++z)
-                    for (int y = 0; y < 3; ++y) {
-                        R *row = fd + wrapi(cz - 1 + z, tg.nz) * tg.plane +
-                                 (int64_t)wrapi(cy - 1 + y, tg.ny) * tg.nx;
-                        const R fzy = fv * wz[z] * wy[y];
-                        for (int x = 0; x < 3; ++x)
-                            unsafeAtomicAdd(row + wrapi(cx - 1 + x, tg.nx), fzy * wx[x]);
+            // three lanes per node, lane j adding the stencil's column x = j
+            // of every (y, z) row: the three additions to one row fall in
+            // one cache line and travel as one atomic request, where a lane
+            // per node sends one request per point (21 nodes per wave)
+            const int lane = tid & 63, j = lane % 3;
+            if (lane < 63)
+                for (int p = (tid >> 6) * 21 + lane / 3; p < N; p += (NT / 64) * 21) {
+                    R wx[3], wy[3], wz[3];
+                    const int cx = delta3<R>(xs[3 * p] * inv_h - mac_off(d, 0), wx);
+                    const int cy = delta3<R>(xs[3 * p + 1] * inv_h - mac_off(d, 1), wy);
+                    const int cz = delta3<R>(xs[3 * p + 2] * inv_h - mac_off(d, 2), wz);
+                    const R fvx = (R)(vals[3 * p + d] * inv_h3) * (j == 0 ? wx[0] : (j == 1 ? wx[1] : wx[2]));
+                    const int64_t ix = wrapi(cx - 1 + j, tg.nx);
+                    int64_t iy[3], iz[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        iy[k] = (int64_t)wrapi(cy - 1 + k, tg.ny) * tg.nx;
+                        iz[k] = (int64_t)wrapi(cz - 1 + k, tg.nz) * tg.plane;
                     }
-            }
+#pragma unroll
+                    for (int z = 0; z < 3; ++z)
+#pragma unroll
+                        for (int y = 0; y < 3; ++y)
+                            unsafeAtomicAdd(fd + iz[z] + iy[y] + ix, fvx * wz[z] * wy[y]);
+                }
         }
     }
 }

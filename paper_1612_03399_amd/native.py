@@ -43,7 +43,7 @@ class ip_grid(C.Structure):
 
 class ip_plan_options(C.Structure):
     _fields_ = [("unit_nodes", C.c_int32), ("patch_owned", C.c_int32), ("tile_bytes", C.c_int32),
-                ("threads", C.c_int32)]
+                ("threads", C.c_int32), ("wg_per_cu", C.c_int32)]
 
 
 class ip_reference(C.Structure):
@@ -197,7 +197,8 @@ class Plan:
         opt = ip_plan_options(int(self.options.get("unit_nodes", 0)),
                               int(self.options.get("patch_owned", 0)),
                               int(self.options.get("tile_bytes", 0)),
-                              int(self.options.get("threads", 0)))
+                              int(self.options.get("threads", 0)),
+                              int(self.options.get("wg_per_cu", 0)))
         _check(LIB.ip_plan_create_ex(C.byref(h), C.byref(m), C.byref(g) if g else None,
                                      IP_F64 if precision == "f64" else IP_F32, C.byref(opt)))
         self.handle = h
@@ -223,8 +224,8 @@ class Plan:
 
 
 def ip_plan_create(mesh, grid=None, precision="f64", options=None) -> Plan:
-    """options: dict with any of unit_nodes, patch_owned, tile_bytes (see
-    ip_plan_options)."""
+    """options: dict with any of unit_nodes, patch_owned, tile_bytes, threads,
+    wg_per_cu (see ip_plan_options)."""
     return Plan(mesh, grid, precision, options)
 
 

@@ -92,7 +92,9 @@ def test_null_arguments_rejected():
     assert N.LIB.ip_plan_destroy(None) == N.IP_OK
 
 
-@pytest.mark.parametrize("opts", [(-1, 0, 0, 0), (0, 8, 0, 0), (0, 0, 1024, 0), (0, 0, 0, 512)])
+@pytest.mark.parametrize("opts", [(-1, 0, 0, 0, 0), (0, 8, 0, 0, 0), (0, 0, 1024, 0, 0),
+                                  (0, 0, 0, 512, 0), (0, 0, 0, 128, 0), (0, 0, 0, 0, 5),
+                                  (0, 0, 0, 0, -1)])
 def test_invalid_plan_options_rejected(opts):
     wl = W.small_suspension(2, 1, 16)
     m, keep = _mesh_struct(wl)

@@ -25,3 +25,42 @@ def test_comparison_is_against_the_current_choice():
 
 def test_margin_is_a_parameter():
     assert choose([r("a", 1.00), r("b", 0.99)], margin=0.0)["options"]["name"] == "b"
+
+
+# ---- the staged search and its cache (host logic) ----
+
+import json  # noqa: E402
+
+from paper_1612_03399_amd import autotune as AT  # noqa: E402
+from paper_1612_03399_amd import workload as W  # noqa: E402
+
+
+def test_stage_candidates_extend_the_best_shape():
+    best1 = {"threads": 384, "wg_per_cu": 2}
+    c2 = AT.staged_candidates(best1)
+    assert len(c2) == len(AT.STAGE2)
+    assert all(c["threads"] == 384 and c["wg_per_cu"] == 2 for c in c2)
+    assert {"threads": 384, "wg_per_cu": 2, "unit_nodes": 384} in c2
+    best2 = c2[0]
+    c3 = AT.staged_candidates(best1, best2)
+    assert all(dict(c, tile_bytes=None) == dict(best2, tile_bytes=None) for c in c3)
+    assert {c["tile_bytes"] for c in c3} == {s["tile_bytes"] for s in AT.STAGE3}
+
+
+def test_signature_separates_workloads_and_precisions():
+    a = W.small_suspension(4, 2, 32)
+    b = W.small_suspension(4, 3, 32)
+    c = W.small_suspension(5, 2, 32)
+    sig = lambda m, p="f64": AT.signature(m, m.grid, p)
+    assert sig(a) == sig(W.small_suspension(4, 2, 32))       # same shape, same key
+    assert len({sig(a), sig(b), sig(c), sig(a, "f32")}) == 4
+
+
+def test_cache_round_trip(tmp_path, monkeypatch):
+    monkeypatch.setenv("IPIBM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    assert AT.cache_load() == {}
+    AT.cache_store("k1", {"options": {"threads": 384}, "results": []})
+    AT.cache_store("k2", {"options": {}, "results": [{"ms": 1.0}]})
+    data = json.load(open(tmp_path / "tune.json"))
+    assert data["k1"]["options"] == {"threads": 384} and data["k2"]["results"] == [{"ms": 1.0}]
+    assert AT.cache_load() == data

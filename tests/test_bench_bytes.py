@@ -44,3 +44,30 @@ def test_matches_brute_force_union_with_wrap():
     for _ in range(5):
         X = rng.uniform(0, 1.0, size=(40, 3)) * np.array([1.2, 1.0, 1.4])
         assert bench.touched_points(X, g) == brute(X, g, bench.MAC_OFFSETS)
+
+
+def test_device_count_matches_numpy():
+    """The torch count the bench uses on large batches (run here on the CPU
+    device) agrees with the numpy union."""
+    rng = np.random.default_rng(4)
+    g = W.Grid(12, 10, 14, 0.1)
+    for _ in range(3):
+        X = rng.uniform(0, 1.0, size=(60, 3)) * np.array([1.2, 1.0, 1.4])
+        assert bench.touched_points_device(X, g, device="cpu") == bench.touched_points(X, g)
+    off = bench.MAC_OFFSETS + ((0.5, 0.5, 0.5),)
+    X = rng.uniform(0, 1.0, size=(30, 3))
+    assert (bench.touched_points_device(X, g, off, device="cpu")
+            == bench.touched_points(X, g, off))
+
+
+def test_parallel_oracle_baseline_reproduces_the_serial_step():
+    """The bench's multi-process oracle (bodies split in ranges, per-process
+    force fields summed by slab) gives the serial oracle's field."""
+    wl = W.small_suspension(6, 2, 32)
+    u = wl.velocity()
+    logs = []
+    out = bench.cpu_baseline(wl, u, logs.append, single_budget_s=0.0)
+    assert out["kind"] == "oracle" and out["single_thread_value"] > 0
+    if out["cores"] > 1:
+        assert out["parallel_field_rel_diff"] <= 1e-13
+        assert out["value"] == out["parallel_value"]

@@ -109,13 +109,26 @@ def uneven_sampled_check(wl, ref, u, options, per_level=16, seed=17):
     return plan
 
 
-def test_uneven_full_sampled():
-    say("full uneven (sampled)")
+@pytest.fixture(scope="module")
+def uneven():
     wl = W.config2()
     ref = O.reference(wl)
     say(f"  {wl.n_bodies} bodies, {wl.n_nodes} nodes; velocity ...")
     u = wl.velocity(dtype=np.float32).astype(np.float64)
-    plan = uneven_sampled_check(wl, ref, u, None)
+    return wl, ref, u
+
+
+#: the default split, and the shape the autotuner picks on this batch (two
+#: 384-thread workgroups per compute unit, most cell boxes in LDS tiles, the
+#: others spread and interpolated directly against the grid)
+UNEVEN_SHAPES = {"default": None, "t384_two_per_cu": {"threads": 384, "wg_per_cu": 2}}
+
+
+@pytest.mark.parametrize("shape", list(UNEVEN_SHAPES))
+def test_uneven_full_sampled(uneven, shape):
+    say("full uneven (sampled)", shape)
+    wl, ref, u = uneven
+    plan = uneven_sampled_check(wl, ref, u, UNEVEN_SHAPES[shape])
     assert plan.patched_bodies > 0      # the level-5 bodies run as patches
 
 

@@ -182,6 +182,9 @@ LAUNCH_SHAPES = {
     "t768_tile8k": {"tile_bytes": 8192},
     "patch256": {"unit_nodes": 768, "patch_owned": 256},
     "patch512": {"unit_nodes": 1536, "patch_owned": 512},
+    "t384_two_per_cu": {"threads": 384, "wg_per_cu": 2},
+    "t256_three_per_cu": {"threads": 256, "wg_per_cu": 3},
+    "t256_small_units": {"threads": 256, "wg_per_cu": 2, "unit_nodes": 384, "patch_owned": 128},
 }
 
 
@@ -194,21 +197,27 @@ def test_step_parity_launch_shapes(case, shape):
     # without a thread count the plan puts units of at most 1536 nodes on
     # 384-thread workgroups and larger ones on 768
     assert plan.fused and plan.step_threads == opts.get("threads", plan.step_threads)
-    assert plan.step_threads in (384, 768)
+    assert plan.step_threads in (256, 384, 768)
 
 
-def test_autotune_choice_computes_the_step():
-    """The autotuner (reference computed from the reference positions with its
-    first plan) returns one of its candidates, times every distinct launch
-    shape, and the shape it picks computes the step to parity."""
+def test_autotune_choice_computes_the_step(tmp_path, monkeypatch):
+    """The autotuner's staged search (reference computed from the reference
+    positions with its first plan) times distinct launch shapes of all three
+    stages, caches its choice (the second call is a lookup returning the same
+    options), and the shape it picks computes the step to parity."""
     from paper_1612_03399_amd import autotune as AT
+    monkeypatch.setenv("IPIBM_TUNE_CACHE", str(tmp_path / "tune.json"))
     say("autotune four_L4_128")
     wl = CASES["four_L4_128"]()
     u = dev(wl.velocity())
-    opts, results = AT.autotune(wl, wl.grid, "f64", dev(wl.X), None, constants(wl), u, wl.dt,
-                                steps=2, warmup=1, Xref=dev(wl.Xref))
-    assert opts in [dict(c) for c in AT.CANDIDATES]
-    assert len(results) >= 2 and all(r["ms"] > 0 for r in results)
+    args = (wl, wl.grid, "f64", dev(wl.X), None, constants(wl), u, wl.dt)
+    opts, results, info = AT.autotune(*args, steps=2, warmup=1, Xref=dev(wl.Xref))
+    assert info["cache"] == "miss"
+    assert len(results) >= 3 and all(r["ms"] > 0 for r in results)
+    assert {r["stage"] for r in results} >= {1, 2}
+    assert opts in [r["options"] for r in results]
+    again, results2, info2 = AT.autotune(*args, steps=2, warmup=1, Xref=dev(wl.Xref))
+    assert info2["cache"] == "hit" and again == opts and results2 == results
     check_step("four_L4_128", "f64", True, opts)
 
 
