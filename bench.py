@@ -598,6 +598,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--bodies", type=int, default=1000)
+    ap.add_argument("--workload", default="suspension", choices=["suspension", "uneven"],
+                    help="headline batch: the 1000-drop suspension on 256^3 (default) or the "
+                         "uneven 4096-body batch on 512^3 (FP32; for its kernel traces and "
+                         "counters)")
     ap.add_argument("--options", default=None,
                     help="launch options as JSON (skips the autotuner), e.g. '{\"threads\": 384}'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -632,7 +636,11 @@ def main():
         del src, dst
         log("copy probe: 512 MiB read + 512 MiB written")
 
-    wl = W.config1(n_bodies=args.bodies, precision=args.precision)
+    if args.workload == "uneven":
+        wl = W.config2()
+        args.precision = "f32"
+    else:
+        wl = W.config1(n_bodies=args.bodies, precision=args.precision)
     log(f"workload {wl.name}: {wl.n_nodes} nodes, {wl.n_edges} edges, {wl.n_faces} faces")
     u_host = wl.velocity(dtype=np.float64)
     stream = torch.cuda.current_stream()

@@ -125,14 +125,17 @@ __device__ __forceinline__ bool edge_forces(const vec3<P> &x1, const vec3<P> &x2
 // (1/6) sum_{f ni i} n_f, so every face hands gv = sV n_f to each of its
 // corners (no anchor cancellation: the anchored terms are ~|x - a| |edge|
 // while their sum is ~|edge|^2).  Returns true if the face is degenerate.
+// nn_out (optional) receives |n| = twice the face's area.
 template <typename P, typename R>
 __device__ __forceinline__ bool face_parts(const vec3<P> &xi, const vec3<P> &xj,
                                            const vec3<P> &xk, R a0, double kA, R sV,
-                                           vec3<R> &gi, vec3<R> &gj, vec3<R> &gk, vec3<R> &gv) {
+                                           vec3<R> &gi, vec3<R> &gj, vec3<R> &gk, vec3<R> &gv,
+                                           R *nn_out = nullptr) {
     const vec3<R> n = cross(to<R>(xj - xi), to<R>(xk - xi));
     const R nn2 = dot(n, n);
     const R inv_nn = rsq_nr(nn2);
     const R nn = nn2 * inv_nn;
+    if (nn_out) *nn_out = nn;
     const R cA = (R)kA * ((R)0.5 * nn - a0) * rcp_nr(a0);    // dW_a/dA
     // -cA * 1/2 nhat x edge = (-cA / (2|n|)) n x edge
     const R sA = (R)-0.5 * cA * inv_nn;
@@ -146,9 +149,10 @@ __device__ __forceinline__ bool face_parts(const vec3<P> &xi, const vec3<P> &xj,
 template <typename P, typename R>
 __device__ __forceinline__ bool face_forces(const vec3<P> &xi, const vec3<P> &xj,
                                             const vec3<P> &xk, R a0, double kA, R sV,
-                                            vec3<R> &gi, vec3<R> &gj, vec3<R> &gk) {
+                                            vec3<R> &gi, vec3<R> &gj, vec3<R> &gk,
+                                            R *nn_out = nullptr) {
     vec3<R> gv;
-    const bool bad = face_parts<P, R>(xi, xj, xk, a0, kA, sV, gi, gj, gk, gv);
+    const bool bad = face_parts<P, R>(xi, xj, xk, a0, kA, sV, gi, gj, gk, gv, nn_out);
     gi = gi + gv;
     gj = gj + gv;
     gk = gk + gv;

@@ -216,7 +216,7 @@ ip_status prepare_step_fused(ip_plan *p);   // one-time launch attributes
 ip_status prepare_mls_units(ip_plan *p);    // one-time launch attributes
 ip_status launch_bind_edge_weights(ip_plan *p, const double *ew, hipStream_t s);
 ip_status launch_pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s);
-// owned nodes of patched units: src -> dst ([N][3] double each)
+// the nodes of patched bodies: src -> dst ([N][3] double each)
 ip_status launch_commit(ip_plan *p, const double *src, double *dst, hipStream_t s);
 // fused reverse step (k_backward.hip), FP64 fused plans; records hold `ref`
 ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference *ref,

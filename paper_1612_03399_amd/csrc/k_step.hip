@@ -11,8 +11,9 @@
 // additions into the grid force field):
 //  P0  positions -> LDS; cell bounding box of the owned nodes (the per-marker
 //      cell index and the body bounding box of Section 5).
-//  P1  enclosed volume and area of a whole body (FP64 block reduction); a
-//      patched body's come from a geometry pass before this kernel.
+//  P1  enclosed volume of a whole body (FP64 block reduction); a patched
+//      body's comes from a geometry pass before this kernel.  The area is
+//      summed from the face loop of P2 and reduced at the end.
 //  P2  face (area + volume) and edge (spring + hinge) elements from the packed
 //      records, their forces added into the node accumulators (ds_add_f64).
 //  P3  counting sort of the owned nodes by Eulerian cell; xs and Fs are
@@ -121,34 +122,30 @@ __global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a
     int kmin[3], kmax[3];
     load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, a.inv_h, kmin, kmax);
 
-    // ---- P1: volume and area (a whole body; a patched body's come from the
-    // geometry pass that precedes this kernel), reduced together with the
-    // bounding box ----
-    double sums[2] = {0.0, 0.0};
+    // ---- P1: volume (a whole body; a patched body's comes from the geometry
+    // pass that precedes this kernel), reduced together with the bounding box ----
+    double sums[1] = {0.0};
     if (whole) {
         const vec3<double> anchor = ldx(xs, 0);
 #pragma unroll
         for (int s = 0; s < FK; ++s) {
             if (fmask & (1u << s)) {
-                double v, ar;
-                face_geometry<double, R>(ldx(xs, fi[s][0]), ldx(xs, fi[s][1]), ldx(xs, fi[s][2]),
-                                         anchor, v, ar);
-                sums[0] += v;
-                sums[1] += ar;
+                const vec3<double> xi = ldx(xs, fi[s][0]), xj = ldx(xs, fi[s][1]),
+                                   xk = ldx(xs, fi[s][2]);
+                sums[0] += dot(xi - anchor, cross(xj - anchor, xk - anchor));
             }
         }
     }
-    block_box_sums<NT, 2>(kmin, kmax, sums, ired, red);
+    block_box_sums<NT, 1>(kmin, kmax, sums, ired, red);
     double Vb;
     if (whole) {
         Vb = sums[0] * (1.0 / 6.0);
-        if (tid == 0) {
-            a.V[b] = Vb;
-            a.A[b] = 0.5 * sums[1];
-        }
+        if (tid == 0) a.V[b] = Vb;
     } else {
         Vb = a.V[b];
     }
+    // twice the area of this thread's faces, from the face forces below
+    double area2 = 0.0;
 
     // ---- P2: elements -> node accumulators ----
     {
@@ -159,8 +156,10 @@ __global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a
             if (fmask & (1u << s)) {
                 const int i = fi[s][0], j = fi[s][1], k = fi[s][2];
                 vec3<R> gi, gj, gk;
+                R nn;
                 bad |= face_forces<double, R>(ldx(xs, i), ldx(xs, j), ldx(xs, k), fa0[s], kA, sV,
-                                              gi, gj, gk);
+                                              gi, gj, gk, &nn);
+                area2 += (double)nn;
                 add3(Fs, i, gi);
                 add3(Fs, j, gj);
                 add3(Fs, k, gk);
@@ -257,9 +256,9 @@ __global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a
             if (pf_ok && d < 2) pf.load(ud + a.field, tg);
         }
         if (use_tile) {
-            for (int p = tid; p < N; p += NT) {
+            // interpolation of node p from the tile (bounds-checked)
+            const auto interp = [&](int p) {
                 R wx[3], wy[3], wz[3];
-                const double xd = xs[3 * p + d];
                 const int cx = delta3<R>(xs[3 * p] * a.inv_h - mac_off(d, 0), wx);
                 const int cy = delta3<R>(xs[3 * p + 1] * a.inv_h - mac_off(d, 1), wy);
                 const int cz = delta3<R>(xs[3 * p + 2] * a.inv_h - mac_off(d, 2), wz);
@@ -276,10 +275,14 @@ __global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a
                             acc += wz[z] * wy[y] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
                         }
                 }
+                return acc;
+            };
+            const auto update = [&](int p, R acc) {
                 const double fd = Fs[3 * p + d];
                 if (!isfinite(fd) || !isfinite((double)acc)) atomicOr(a.status, IP_STATUS_NONFINITE);
-                Fs[3 * p + d] = xd + a.dt * (double)acc + cm * (double)(R)fd;
-            }
+                Fs[3 * p + d] = xs[3 * p + d] + a.dt * (double)acc + cm * (double)(R)fd;
+            };
+            for (int p = tid; p < N; p += NT) update(p, interp(p));
         } else {
             // directly from the grid, three lanes per node (21 nodes per
             // wave): lane j reads column x = j of the stencil's nine rows,
@@ -326,6 +329,10 @@ __global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a
         }
         if (use_tile) lds_barrier();
     }
+    // the body's area (whole bodies; a patched body's comes from the geometry
+    // pass): per-wave sums of the face loop's |n|, added in wave order below
+    area2 = wave_sum(area2);
+    if ((tid & 63) == 0) red[tid >> 6] = area2;
     __syncthreads();
     // back to node order (pinned nodes keep their position), staged in xs;
     // a whole body is written in place, once and coalesced, a patch into the
@@ -341,6 +348,11 @@ __global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a
         }
     }
     __syncthreads();
+    if (whole && tid == 0) {
+        double ar = 0.0;
+        for (int v = 0; v < NT / 64; ++v) ar += red[v];
+        a.A[b] = 0.5 * ar;
+    }
     if (whole) {
         for (int i = tid; i < 3 * N; i += NT) a.X[3 * n0 + i] = xs[i];
     } else {
@@ -403,27 +415,24 @@ void pack_reference(ip_plan *p, const ip_reference *ref, hipStream_t s) {
                            (const R *)ref->A0, (FaceRec<R> *)p->face_rec);
 }
 
-// Results of patched bodies: staging array -> destination (owned nodes of
-// each patch unit; one workgroup per unit).
-__global__ void k_commit(const int32_t *__restrict__ units, const int64_t *__restrict__ noff,
-                         const int32_t *__restrict__ owned, const int32_t *__restrict__ nodes,
-                         const double *__restrict__ Xstage, double *__restrict__ X) {
-    const int w = units[blockIdx.x];
-    const int32_t *gid = nodes + noff[2 * w];
-    for (int j = threadIdx.x; j < owned[w]; j += blockDim.x) {
-        const int64_t g = gid[j];
-        X[3 * g] = Xstage[3 * g];
-        X[3 * g + 1] = Xstage[3 * g + 1];
-        X[3 * g + 2] = Xstage[3 * g + 2];
-    }
+// Results of patched bodies: staging array -> destination.  The patches of
+// a body own each of its nodes exactly once, so a patched body's whole node
+// range is copied, contiguous and coalesced (one workgroup per body).
+__global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ bodies,
+                                                const int64_t *__restrict__ node_off,
+                                                const double *__restrict__ Xstage,
+                                                double *__restrict__ X) {
+    const int b = bodies[blockIdx.x];
+    const int64_t i0 = 3 * node_off[b], i1 = 3 * node_off[b + 1];
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) X[i] = Xstage[i];
 }
 
 }  // namespace
 
 ip_status launch_commit(ip_plan *p, const double *src, double *dst, hipStream_t s) {
-    if (p->n_patched_units == 0) return IP_OK;
-    hipLaunchKernelGGL(k_commit, dim3(p->n_patched_units), dim3(256), 0, s, p->patched_units,
-                       p->wu_noff, p->wu_owned, p->wu_nodes, src, dst);
+    if (p->n_patched_bodies == 0) return IP_OK;
+    hipLaunchKernelGGL(k_commit, dim3(p->n_patched_bodies), dim3(256), 0, s, p->patched_bodies,
+                       p->node_off, src, dst);
     IP_HIP_CHECK(hipGetLastError());
     return IP_OK;
 }
@@ -538,10 +547,5 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
         }
         IP_HIP_CHECK(hipGetLastError());
     }
-    if (p->n_patched_units > 0) {
-        hipLaunchKernelGGL(k_commit, dim3(p->n_patched_units), dim3(256), 0, s, p->patched_units,
-                           p->wu_noff, p->wu_owned, p->wu_nodes, p->Xstage, X);
-        IP_HIP_CHECK(hipGetLastError());
-    }
-    return IP_OK;
+    return launch_commit(p, p->Xstage, X, s);
 }

@@ -327,8 +327,9 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
     // carry weight only from nodes whose stencil centre is the cell (first)
     // or the next one (last)
     bool used0 = false, used3 = false;
-    for (int p = p0; p < p1; ++p) {
-        R wx[4], wy[4], wz[4];
+    // weights of node p on this lattice, with its stencil shifted into the
+    // block along the unstaggered axis
+    const auto weights = [&](int p, R wx[4], R wy[4], R wz[4], bool &u0, bool &u3, bool &bd) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             R w3[3];
@@ -341,17 +342,18 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
                 w[1] = s1 ? w3[0] : w3[1];
                 w[2] = s1 ? w3[1] : w3[2];
                 w[3] = s1 ? w3[2] : (R)0;
-                used0 |= !s1;
-                used3 |= s1;
-                if (sh != 0 && sh != 1) bad = true;
+                u0 = !s1;
+                u3 = s1;
+                bd = bd || (sh != 0 && sh != 1);
             } else {
                 w[0] = w3[0];
                 w[1] = w3[1];
                 w[2] = w3[2];
-                if (sh != 0) bad = true;
+                bd = bd || sh != 0;
             }
         }
-        const R fd = (R)(Fs[3 * p + D] * inv_h3);
+    };
+    const auto accumulate = [&](R fd, const R wx[4], const R wy[4], const R wz[4]) {
 #pragma unroll
         for (int z = 0; z < Dm::LZ; ++z) {
             const R fz = fd * wz[z];
@@ -362,6 +364,15 @@ __device__ __forceinline__ void spread_cell(const double *xs, const double *Fs, 
                 for (int x = 0; x < Dm::LX; ++x) acc[z][y][x] += fzy * wx[x];
             }
         }
+    };
+    for (int p = p0; p < p1; ++p) {
+        R wx[4], wy[4], wz[4];
+        bool u0 = false, u3 = false, bd = false;
+        weights(p, wx, wy, wz, u0, u3, bd);
+        used0 |= u0;
+        used3 |= u3;
+        bad |= bd;
+        accumulate((R)(Fs[3 * p + D] * inv_h3), wx, wy, wz);
     }
     // block origin in tile coordinates: point k - 1 is tile index k - kmin.
     // The tile spans the cells' box with one point below and two above, so

@@ -144,3 +144,4 @@ def energy_error(Wg, Wo, Vg, Vo, wl, V0, tol):
     with np.errstate(divide="ignore", invalid="ignore"):
         r = np.where(bar > 0, diff / np.where(bar > 0, bar, 1.0), np.where(diff > 0, np.inf, 0.0))
     return float(r.max()) if r.size else 0.0
+

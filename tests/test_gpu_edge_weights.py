@@ -113,8 +113,9 @@ def test_unit_weights_give_the_unweighted_bits(case):
     _, _, X0, f0 = weighted_step(wl, ref, "f64", None)
     _, _, X1, f1 = weighted_step(wl, ref, "f64", np.ones((wl.n_edges, 2)))
     assert np.array_equal(X0, X1)
-    # spreading adds with atomics: the field agrees to rounding, not bits
-    assert rel_inf(f1, f0) <= 1e-14
+    # the forces add in LDS and the field with atomics, both in a
+    # run-dependent order: the field agrees to that rounding, normwise
+    assert rel_inf(f1, f0) <= 1e-13
     plan = N.Plan(wl, wl.grid, "f64")
     gref = gpu_reference_from_oracle(ref, "f64")
     Fa = host(N.ip_forces(plan, dev(wl.X), gref, constants(wl)))

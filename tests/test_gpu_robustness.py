@@ -53,8 +53,12 @@ def test_step_repeatable(case):
     e_x = body_rel(X1 - wl.X, X2 - wl.X, wl.node_off)
     e_f = rel_inf(f1, f2)
     say(f"  dX {e_x:.1e}  f {e_f:.1e}")
-    # a few ulps of the largest terms of each sum, relative to the sum
-    assert e_x <= 1e-13 and e_f <= 1e-14
+    # a few ulps of the largest terms of each sum, relative to the sum; the
+    # field carries the run-dependent rounding of both the nodes' force sums
+    # (elements added in LDS in any order; at a node where they nearly
+    # cancel, a large relative change of a small force) and the grid
+    # additions, so it is held normwise over the field
+    assert e_x <= 1e-13 and e_f <= 1e-13
     # the pieces computed without atomics are bitwise repeatable
     U1 = host(N.ibm_interp(plan, dev(wl.X), u))
     U2 = host(N.ibm_interp(plan, dev(wl.X), u))
