@@ -59,5 +59,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+PROBES = os.path.join(PKG, "probes")
+
+
+def build_probes(verbose: bool = False) -> list:
+    """Measurement programs beside the library (probes/*.hip -> executables)."""
+    out = []
+    for src in sorted(f for f in os.listdir(PROBES) if f.endswith(".hip")):
+        exe = os.path.join(PROBES, src[:-4])
+        cmd = [hipcc(), *HIPCC_FLAGS, os.path.join(PROBES, src), "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for probes/{src}:\n{r.stderr}")
+        out.append(exe)
+        if verbose:
+            print("built", exe)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
