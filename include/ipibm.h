@@ -128,12 +128,12 @@ typedef struct {
  *               left once the largest unit's arrays are placed; at least
  *               4096);
  *   threads     threads per workgroup of the fused kernel, with units of at
- *               most 4 x threads nodes: 768, 384 or 256 for every unit; by
+ *               most 4 x threads nodes: 768, 384, 256 or 128 for every unit; by
  *               default units above 1536 nodes run on 768 threads and the
  *               others on 384;
  *   wg_per_cu   workgroups per compute unit the tile of the smaller-unit
  *               launch (the only one when `threads` is set) is sized for:
- *               1 to 4 (default 2 for the 384-thread launch of the default
+ *               1 to 8 (default 2 for the 384-thread launch of the default
  *               split, else 1).  The LDS left per workgroup, once the
  *               largest unit's arrays are placed, is the tile; a unit whose
  *               cell box does not fit it spreads and interpolates directly

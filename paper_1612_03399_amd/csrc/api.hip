@@ -330,9 +330,9 @@ ip_status ip_plan_create_ex(ip_plan **plan, const ip_mesh *mesh, const ip_grid *
         if (opt.unit_nodes < 0 || opt.patch_owned < 0 || opt.tile_bytes < 0 ||
             (opt.patch_owned > 0 && opt.patch_owned < 16) ||
             (opt.tile_bytes > 0 && opt.tile_bytes < 4096) ||
-            (opt.threads != 0 && opt.threads != 256 && opt.threads != 384 &&
-             opt.threads != 768) ||
-            opt.wg_per_cu < 0 || opt.wg_per_cu > 4)
+            (opt.threads != 0 && opt.threads != 128 && opt.threads != 256 &&
+             opt.threads != 384 && opt.threads != 768) ||
+            opt.wg_per_cu < 0 || opt.wg_per_cu > 8)
             return arg_error("invalid plan options");
     }
     ip_plan *p = new ip_plan();

@@ -463,7 +463,7 @@ struct VjpArgs {
 
 // EW: the edges carry per-edge weights on ks and kb (record order).
 template <int NT, bool EW>
-__global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_vjp_fused(VjpArgs a) {
+__global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[4 * (NT / 64)];
     __shared__ int ired[6 * (NT / 64)];
@@ -889,10 +889,12 @@ ip_status prepare_step_vjp_fused(ip_plan *p) {
         const auto &sc = p->step_class[c];
         const int lds = (int)step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
         const void *fns[2] = {
-            sc.threads == 256   ? (const void *)k_step_vjp_fused<256, false>
+            sc.threads == 128   ? (const void *)k_step_vjp_fused<128, false>
+            : sc.threads == 256 ? (const void *)k_step_vjp_fused<256, false>
             : sc.threads == 384 ? (const void *)k_step_vjp_fused<384, false>
                                 : (const void *)k_step_vjp_fused<768, false>,
-            sc.threads == 256   ? (const void *)k_step_vjp_fused<256, true>
+            sc.threads == 128   ? (const void *)k_step_vjp_fused<128, true>
+            : sc.threads == 256 ? (const void *)k_step_vjp_fused<256, true>
             : sc.threads == 384 ? (const void *)k_step_vjp_fused<384, true>
                                 : (const void *)k_step_vjp_fused<768, true>};
         for (const void *fn : fns)
@@ -957,7 +959,12 @@ ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference 
         a.tile_bytes = sc.tile_bytes;
         const size_t lds = step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
         const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
-        if (sc.threads == 256) {
+        if (sc.threads == 128) {
+            if (a.ew)
+                hipLaunchKernelGGL((k_step_vjp_fused<128, true>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((k_step_vjp_fused<128, false>), grid, block, lds, s, a);
+        } else if (sc.threads == 256) {
             if (a.ew)
                 hipLaunchKernelGGL((k_step_vjp_fused<256, true>), grid, block, lds, s, a);
             else

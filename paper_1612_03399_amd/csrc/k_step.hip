@@ -53,10 +53,10 @@ struct StepArgs {
 };
 
 // EW: the edges carry per-edge weights on ks and kb (record order).
-// NT = 256 workgroups are meant to share a compute unit three at a time,
-// which caps their registers at 168.
+// NT = 256 and 128 workgroups are meant to share a compute unit three to six
+// at a time, which caps their registers at 168.
 template <typename R, int NT, bool EW>
-__global__ __launch_bounds__(NT, NT == 256 ? 3 : 1) void k_step_fused(StepArgs a) {
+__global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_fused(StepArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ double red[2 * (NT / 64)];
     __shared__ int ired[6 * (NT / 64)];
@@ -453,7 +453,8 @@ size_t step_fused_lds_bytes(int nmax, int tile_bytes) {
 
 template <typename R, bool EW>
 const void *step_kernel(int threads) {
-    return threads == 256   ? (const void *)k_step_fused<R, 256, EW>
+    return threads == 128   ? (const void *)k_step_fused<R, 128, EW>
+           : threads == 256 ? (const void *)k_step_fused<R, 256, EW>
            : threads == 384 ? (const void *)k_step_fused<R, 384, EW>
                             : (const void *)k_step_fused<R, 768, EW>;
 }
@@ -531,14 +532,18 @@ ip_status launch_step_fused(ip_plan *p, double *X, const ip_reference *ref,
         const size_t lds = step_fused_lds_bytes(sc.nmax, sc.tile_bytes);
         const dim3 grid(sc.unit_end - sc.unit_begin), block(sc.threads);
         if (p->prec == IP_F64) {
-            if (sc.threads == 256)
+            if (sc.threads == 128)
+                launch_step_variant<double, 128>(grid, block, lds, s, a);
+            else if (sc.threads == 256)
                 launch_step_variant<double, 256>(grid, block, lds, s, a);
             else if (sc.threads == 384)
                 launch_step_variant<double, 384>(grid, block, lds, s, a);
             else
                 launch_step_variant<double, 768>(grid, block, lds, s, a);
         } else {
-            if (sc.threads == 256)
+            if (sc.threads == 128)
+                launch_step_variant<float, 128>(grid, block, lds, s, a);
+            else if (sc.threads == 256)
                 launch_step_variant<float, 256>(grid, block, lds, s, a);
             else if (sc.threads == 384)
                 launch_step_variant<float, 384>(grid, block, lds, s, a);

@@ -447,7 +447,8 @@ __device__ __forceinline__ void load_positions(double *xs, const double *X, bool
                                                int lo[3], int hi[3]) {
     const int tid = threadIdx.x;
     if (whole) {
-        copy_to_lds<NT>(xs, X + 3 * n0, 3 * NL);
+        // one round of loads in flight for the largest unit (4 NT nodes)
+        copy_to_lds<NT, double, 12>(xs, X + 3 * n0, 3 * NL);
     } else {
         for (int i = tid; i < NL; i += NT) {
             const int64_t g = gid[i];

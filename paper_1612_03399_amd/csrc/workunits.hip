@@ -326,11 +326,15 @@ bool build_work_units(const ip_mesh *m, int whole_max, int nmax_unit, int fmax_u
         out.face_lid.insert(out.face_lid.end(), p.face_lid.begin(), p.face_lid.end());
         p = WorkUnits{};
     }
-    // largest units first (the tail of the launch runs the small ones)
+    // largest units first (the tail of the launch runs the small ones), in
+    // size classes of 64 nodes; within a class the patches of a body stay
+    // together, so that units running side by side share their grid lines
     std::vector<int32_t> idx(out.units.size());
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
-        return out.units[x].n_nodes > out.units[y].n_nodes;
+        const int cx = out.units[x].n_nodes / 64, cy = out.units[y].n_nodes / 64;
+        if (cx != cy) return cx > cy;
+        return out.units[x].body < out.units[y].body;
     });
     std::vector<WorkUnitHost> sorted;
     sorted.reserve(idx.size());

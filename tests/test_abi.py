@@ -93,7 +93,7 @@ def test_null_arguments_rejected():
 
 
 @pytest.mark.parametrize("opts", [(-1, 0, 0, 0, 0), (0, 8, 0, 0, 0), (0, 0, 1024, 0, 0),
-                                  (0, 0, 0, 512, 0), (0, 0, 0, 128, 0), (0, 0, 0, 0, 5),
+                                  (0, 0, 0, 512, 0), (0, 0, 0, 64, 0), (0, 0, 0, 0, 9),
                                   (0, 0, 0, 0, -1)])
 def test_invalid_plan_options_rejected(opts):
     wl = W.small_suspension(2, 1, 16)

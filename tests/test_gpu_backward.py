@@ -43,10 +43,10 @@ def say(*a):
     print(*a, flush=True)
 
 
-def setup(case):
+def setup(case, options=None):
     wl = CASES[case]()
     ref = O.reference(wl)
-    plan = N.Plan(wl, wl.grid, "f64")
+    plan = N.Plan(wl, wl.grid, "f64", options)
     return wl, ref, plan, gpu_reference_from_oracle(ref, "f64"), constants(wl)
 
 
@@ -81,7 +81,26 @@ def test_forces_jvp_symmetric():
 @pytest.mark.parametrize("case", list(CASES))
 def test_step_vjp_parity(case):
     say("step_vjp", case)
-    wl, ref, plan, gref, k = setup(case)
+    check_step_vjp(case)
+
+
+#: workgroup shapes of the fused reverse step besides the default
+VJP_SHAPES = {
+    "t256_small_units": {"threads": 256, "wg_per_cu": 2, "unit_nodes": 384, "patch_owned": 128},
+    "t128_four_per_cu": {"threads": 128, "wg_per_cu": 4, "patch_owned": 256},
+}
+
+
+@pytest.mark.parametrize("shape", list(VJP_SHAPES))
+@pytest.mark.parametrize("case", ["uneven_small", "ventricle_patched"])
+def test_step_vjp_launch_shapes(case, shape):
+    say("step_vjp shape", case, shape)
+    plan = check_step_vjp(case, VJP_SHAPES[shape])
+    assert plan.step_threads == VJP_SHAPES[shape]["threads"]
+
+
+def check_step_vjp(case, options=None):
+    wl, ref, plan, gref, k = setup(case, options)
     u = wl.velocity(dtype=np.float64)
     dt = wl.dt
     rng = np.random.default_rng(9)
@@ -114,6 +133,7 @@ def test_step_vjp_parity(case):
     lam_in = dev(lam1)
     N.ip_step_vjp(plan, dev(wl.X), gref, k, dev(u), dt, lam_in, lam=lam_in)
     assert per_body_rel(host(lam_in) - lam1, want_lam - lam1, wl.node_off) <= TOL
+    return plan
 
 
 @pytest.mark.parametrize("case", ["drop_L3_64", "four_L2_32", "uneven_small"])

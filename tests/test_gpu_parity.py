@@ -185,6 +185,7 @@ LAUNCH_SHAPES = {
     "t384_two_per_cu": {"threads": 384, "wg_per_cu": 2},
     "t256_three_per_cu": {"threads": 256, "wg_per_cu": 3},
     "t256_small_units": {"threads": 256, "wg_per_cu": 2, "unit_nodes": 384, "patch_owned": 128},
+    "t128_four_per_cu": {"threads": 128, "wg_per_cu": 4, "patch_owned": 256},
 }
 
 
@@ -197,7 +198,7 @@ def test_step_parity_launch_shapes(case, shape):
     # without a thread count the plan puts units of at most 1536 nodes on
     # 384-thread workgroups and larger ones on 768
     assert plan.fused and plan.step_threads == opts.get("threads", plan.step_threads)
-    assert plan.step_threads in (256, 384, 768)
+    assert plan.step_threads in (128, 256, 384, 768)
 
 
 def test_autotune_choice_computes_the_step(tmp_path, monkeypatch):
