@@ -5,20 +5,28 @@
 // spreading factor c_l), and the transfer of centroid forces to the triangle
 // vertices (one third per vertex, Section 2.3).
 //
-// One thread per marker.  The weight is a product over axes, W_k =
-// wx_i wy_j wz_k with w(r) = exp(-(r/alpha)^2), r = |x_a - x^k_a| / 1.5 h, so
-// every entry of the moment matrix A = sum_k W_k p_k p_k^T (p_k = [1, dx_i,
-// dy_j, dz_k], offsets about the marker in units of h) is a product of three
-// per-axis sums S0 = sum w, S1 = sum w d, S2 = sum w d^2.  A is symmetric
-// positive definite (all 27 weights are positive inside the support); its
-// Cholesky factor gives z = A^{-1} e_0 and phi_ijk = W_ijk (z0 + z1 dx_i +
-// z2 dy_j + z3 dz_k).  All MLS arithmetic is FP64; the fields are R.
+// The weight is a product over axes, W_k = wx_i wy_j wz_k with w(r) =
+// exp(-(r/alpha)^2), r = |x_a - x^k_a| / 1.5 h, and the shape functions do not
+// change when the weights of one axis are scaled (A and A^{-1} B scale
+// inversely), so each axis's three weights are normalised to sum one.  With
+// the per-axis mean m_a and variance v_a of the offsets d_a = (x^k_a - x_a)/h
+// under those weights, the moment matrix of the linear basis p = [1, dx, dy,
+// dz] is A = S (pm pm^T + diag(0, v_x, v_y, v_z)), pm = [1, m_x, m_y, m_z],
+// S the product of the weight sums, and its inverse is closed-form: the
+// weighted linear fit of values q_k has gradient coefficients
+//   a_a = sum_k Wn_k (d_a - m_a) q_k / v_a        (a = x, y, z)
+// and value a_0 = sum_k Wn_k q_k - sum_a m_a a_a (Wn the normalised weight
+// product), and the shape functions are
+//   phi_ijk = Wn_ijk (1 - sum_a m_a (d_a - m_a) / v_a).
+// Every sum over the 27 points is separable (rows of three along x, then y,
+// then z), so no moment matrix is formed or solved.  All MLS arithmetic is
+// FP64; the fields are R.
 //
 // The per-axis parts are shared: along any axis the three MAC lattices sit at
 // only two offsets (integer or half cells), so a marker computes six axes for
-// all three lattices (the probe kernel excepted, see there); the three weights of an axis take two exponentials
-// (w_{c-1,c+1} = w_c exp(-q^2) exp(+-2 d_c q^2)); and the Cholesky factor keeps
-// the reciprocals of its diagonal, so each solve is four divisions.
+// all three lattices (the probe kernel excepted, see there), and the three
+// weights of an axis take one exponential (scaled by exp(2 d_c q^2) / w_c they
+// are exp(-q^2) exp(2 d_c q^2)^2, exp(2 d_c q^2), exp(-q^2)).
 //
 // Interpolation runs one thread per marker (its gathers of u hit in L2: the
 // faces of a body are consecutive).  Spreading on plans with work units runs
@@ -43,17 +51,19 @@ struct MlsGrid {
     // weight w(d) = exp(-(|d| q)^2), q = 1 / (1.5 alpha), d in cells
     double inv_alpha;
     double q2, cq;       // q^2 and exp(-q^2)
+
     int fast;            // q^2 small enough for the two-exponential form
 };
 
 // One axis of a marker's MLS shape on lattices with a given offset along
 // that axis: the three support points c - 1, c, c + 1 around the marker.
 struct MlsAxis {
-    double w[3];         // weights
-    double dk[3];        // offsets (x^k - x) / h
+    double w[3];         // weights, normalised to sum one
+    double e[3];         // gradient weights w_j (d_j - m) / v
+    double m;            // mean offset sum_j w_j d_j (offsets d_j = (x^k - x) / h)
     int idx[3];          // wrapped lattice indices
     int c;               // unwrapped index of the middle point
-    double s0, s1, s2;   // sum w, sum w d, sum w d^2
+    bool ok;             // weights and variance finite, variance positive
 };
 
 __device__ __forceinline__ void mls_axis(double xa, double off, int n, const MlsGrid &g,
@@ -61,143 +71,164 @@ __device__ __forceinline__ void mls_axis(double xa, double off, int n, const Mls
     const double s = xa * g.inv_h - off;
     double c = floor(s + 0.5);
     if (!(fabs(c) < 1.0e9)) c = 0.0;           // non-finite or absurd position
+    double dk[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        A.dk[j] = (c - 1.0 + j) - s;
-        A.idx[j] = wrapi((int)c - 1 + j, n);
-    }
+    for (int j = 0; j < 3; ++j) dk[j] = (c - 1.0 + j) - s;
+    const int m = wrapi((int)c, n);
+    A.idx[0] = m == 0 ? n - 1 : m - 1;
+    A.idx[1] = m;
+    A.idx[2] = m == n - 1 ? 0 : m + 1;
     A.c = (int)c;
-    const double r1 = fabs(A.dk[1]) * (1.0 / 1.5) * g.inv_alpha;
-    const double w1 = exp(-r1 * r1);
-    double w0, w2;
+    double w0, w1, w2;
     if (g.fast) {
-        // (d1 -+ 1)^2 q^2 = d1^2 q^2 -+ 2 d1 q^2 + q^2, so the outer weights
-        // are w1 exp(-q^2) exp(+-2 d1 q^2): two exponentials per axis
-        const double E = exp(2.0 * A.dk[1] * g.q2);
-        w0 = w1 * g.cq * E;
-        w2 = w1 * g.cq / E;
+        // (d1 -+ 1)^2 q^2 = d1^2 q^2 -+ 2 d1 q^2 + q^2: relative to the middle
+        // weight the outer ones are exp(-q^2) exp(+-2 d1 q^2); scaled by
+        // E = exp(2 d1 q^2) (|d1| <= 1/2, q^2 <= 200: all in range)
+        const double E = exp(2.0 * dk[1] * g.q2);
+        w0 = g.cq * E * E;
+        w1 = E;
+        w2 = g.cq;
     } else {
-        const double r0 = fabs(A.dk[0]) * (1.0 / 1.5) * g.inv_alpha;
-        const double r2 = fabs(A.dk[2]) * (1.0 / 1.5) * g.inv_alpha;
+        const double r0 = fabs(dk[0]) * (1.0 / 1.5) * g.inv_alpha;
+        const double r1 = fabs(dk[1]) * (1.0 / 1.5) * g.inv_alpha;
+        const double r2 = fabs(dk[2]) * (1.0 / 1.5) * g.inv_alpha;
         w0 = exp(-r0 * r0);
+        w1 = exp(-r1 * r1);
         w2 = exp(-r2 * r2);
     }
-    A.w[0] = fabs(A.dk[0]) <= 1.5 ? w0 : 0.0;
-    A.w[1] = fabs(A.dk[1]) <= 1.5 ? w1 : 0.0;
-    A.w[2] = fabs(A.dk[2]) <= 1.5 ? w2 : 0.0;
-    A.s0 = A.s1 = A.s2 = 0.0;
+    w0 = fabs(dk[0]) <= 1.5 ? w0 : 0.0;
+    w1 = fabs(dk[1]) <= 1.5 ? w1 : 0.0;
+    w2 = fabs(dk[2]) <= 1.5 ? w2 : 0.0;
+    const double inv_s = rcp_nr(w0 + w1 + w2);
+    A.w[0] = w0 * inv_s;
+    A.w[1] = w1 * inv_s;
+    A.w[2] = w2 * inv_s;
+    A.m = A.w[0] * dk[0] + A.w[1] * dk[1] + A.w[2] * dk[2];
+    double v = 0.0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A.s0 += A.w[j];
-        A.s1 += A.w[j] * A.dk[j];
-        A.s2 += A.w[j] * A.dk[j] * A.dk[j];
+        dk[j] -= A.m;
+        v += A.w[j] * dk[j] * dk[j];
     }
+    const double inv_v = rcp_nr(v);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A.e[j] = A.w[j] * dk[j] * inv_v;
+    A.ok = isfinite(inv_s) && isfinite(inv_v) && isfinite(A.m) && v > 0.0;
 }
 
-// Both offsets of every axis for one marker: o0 (lattice points at integer
-// cells along the axis) and o5 (at half cells).  MAC lattice d is offset 0
-// along axis d and 1/2 along the others; the cell-centred lattice is 1/2
-// along all three.
-struct MlsAxes {
-    MlsAxis o0[3], o5[3];
+// The half-cell axes of a marker.  MAC lattice d sits at integer cells along
+// axis d and at half cells along the other two (the cell-centred lattice at
+// half cells along all three), so each half-cell axis serves two of the three
+// MAC lattices; the integer-cell axis of lattice d is computed when lattice d
+// is reached (fewer axes live at once).
+struct MlsHalf {
+    MlsAxis h[3];
 };
 
-__device__ __forceinline__ void mls_axes(const vec3<double> &x, const MlsGrid &g, MlsAxes &M) {
-    const double xs[3] = {x.x, x.y, x.z};
-    const int n[3] = {g.nx, g.ny, g.nz};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        mls_axis(xs[a], 0.0, n[a], g, M.o0[a]);
-        mls_axis(xs[a], 0.5, n[a], g, M.o5[a]);
-    }
+__device__ __forceinline__ void mls_half_axes(const vec3<double> &x, const MlsGrid &g, MlsHalf &H) {
+    mls_axis(x.x, 0.5, g.nx, g, H.h[0]);
+    mls_axis(x.y, 0.5, g.ny, g, H.h[1]);
+    mls_axis(x.z, 0.5, g.nz, g, H.h[2]);
 }
 
-// Cholesky factor of the moment matrix A (symmetric, entries products of the
-// per-axis sums: A_00 = X0 Y0 Z0, A_01 = X1 Y0 Z0, ...) with the reciprocals
-// of its diagonal, and the solve of A x = b with it.
-struct MlsChol {
-    double l10, l20, l30, l21, l31, l32;
-    double r0, r1, r2, r3;   // 1 / l_ii
-};
-
-__device__ __forceinline__ void mls_factor(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
-                                           MlsChol &L) {
-    const double a00 = X.s0 * Y.s0 * Z.s0;
-    const double a01 = X.s1 * Y.s0 * Z.s0, a02 = X.s0 * Y.s1 * Z.s0, a03 = X.s0 * Y.s0 * Z.s1;
-    const double a11 = X.s2 * Y.s0 * Z.s0, a22 = X.s0 * Y.s2 * Z.s0, a33 = X.s0 * Y.s0 * Z.s2;
-    const double a12 = X.s1 * Y.s1 * Z.s0, a13 = X.s1 * Y.s0 * Z.s1, a23 = X.s0 * Y.s1 * Z.s1;
-    L.r0 = 1.0 / sqrt(a00);
-    L.l10 = a01 * L.r0;
-    L.l20 = a02 * L.r0;
-    L.l30 = a03 * L.r0;
-    L.r1 = 1.0 / sqrt(a11 - L.l10 * L.l10);
-    L.l21 = (a12 - L.l20 * L.l10) * L.r1;
-    L.l31 = (a13 - L.l30 * L.l10) * L.r1;
-    L.r2 = 1.0 / sqrt(a22 - L.l20 * L.l20 - L.l21 * L.l21);
-    L.l32 = (a23 - L.l30 * L.l20 - L.l31 * L.l21) * L.r2;
-    L.r3 = 1.0 / sqrt(a33 - L.l30 * L.l30 - L.l31 * L.l31 - L.l32 * L.l32);
+__device__ __forceinline__ void mls_int_axis(const vec3<double> &x, int d, const MlsGrid &g,
+                                             MlsAxis &I) {
+    mls_axis(d == 0 ? x.x : d == 1 ? x.y : x.z, 0.0, d == 0 ? g.nx : d == 1 ? g.ny : g.nz, g, I);
 }
 
-__device__ __forceinline__ bool mls_solve(const MlsChol &L, const double b[4], double x[4]) {
-    const double y0 = b[0] * L.r0;
-    const double y1 = (b[1] - L.l10 * y0) * L.r1;
-    const double y2 = (b[2] - L.l20 * y0 - L.l21 * y1) * L.r2;
-    const double y3 = (b[3] - L.l30 * y0 - L.l31 * y1 - L.l32 * y2) * L.r3;
-    x[3] = y3 * L.r3;
-    x[2] = (y2 - L.l32 * x[3]) * L.r2;
-    x[1] = (y1 - L.l21 * x[2] - L.l31 * x[3]) * L.r1;
-    x[0] = (y0 - L.l10 * x[1] - L.l20 * x[2] - L.l30 * x[3]) * L.r0;
-    return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(x[3]);
+// Axes of MAC lattice d from the half-cell axes and its integer-cell axis I
+// (d a compile-time constant after unrolling, so the axes stay in registers).
+__device__ __forceinline__ const MlsAxis &axis_x(const MlsHalf &H, const MlsAxis &I, int d) {
+    return d == 0 ? I : H.h[0];
+}
+__device__ __forceinline__ const MlsAxis &axis_y(const MlsHalf &H, const MlsAxis &I, int d) {
+    return d == 1 ? I : H.h[1];
+}
+__device__ __forceinline__ const MlsAxis &axis_z(const MlsHalf &H, const MlsAxis &I, int d) {
+    return d == 2 ? I : H.h[2];
 }
 
-// The shape of one marker on one lattice: per-axis parts and z = A^{-1} e_0.
-struct MlsShape {
-    double w[3][3];      // per-axis weights of the 3 support points
-    double dk[3][3];     // per-axis offsets (x^k - x) / h
-    double z[4];         // A^{-1} e_0
-    int idx[3][3];       // wrapped lattice indices per axis
-    int c[3];            // unwrapped index of the middle support point per axis
-};
-
-__device__ __forceinline__ bool mls_shape(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
-                                          MlsShape &S) {
-    const MlsAxis *ax[3] = {&X, &Y, &Z};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            S.w[a][j] = ax[a]->w[j];
-            S.dk[a][j] = ax[a]->dk[j];
-            S.idx[a][j] = ax[a]->idx[j];
-        }
-        S.c[a] = ax[a]->c;
-    }
-    MlsChol L;
-    mls_factor(X, Y, Z, L);
-    const double e0[4] = {1.0, 0.0, 0.0, 0.0};
-    return mls_solve(L, e0, S.z);
-}
-
-// Shape on MAC lattice d from a marker's shared axes (d a compile-time
-// constant after unrolling, so the axes stay in registers).
-__device__ __forceinline__ bool mls_shape(const MlsAxes &M, int d, MlsShape &S) {
-    return mls_shape(d == 0 ? M.o0[0] : M.o5[0], d == 1 ? M.o0[1] : M.o5[1],
-                     d == 2 ? M.o0[2] : M.o5[2], S);
-}
-
-// Shape on MAC lattice d at x, every axis computed here.
-__device__ __forceinline__ bool mls_shape(const vec3<double> &x, int d, const MlsGrid &g,
-                                          MlsShape &S) {
-    MlsAxis X, Y, Z;
+// The three axes of MAC lattice d at x, computed here.
+__device__ __forceinline__ void mls_axes(const vec3<double> &x, int d, const MlsGrid &g,
+                                         MlsAxis &X, MlsAxis &Y, MlsAxis &Z) {
     mls_axis(x.x, mac_off(d, 0), g.nx, g, X);
     mls_axis(x.y, mac_off(d, 1), g.ny, g, Y);
     mls_axis(x.z, mac_off(d, 2), g.nz, g, Z);
-    return mls_shape(X, Y, Z, S);
 }
 
-__device__ __forceinline__ double mls_phi(const MlsShape &S, int i, int j, int k) {
-    return S.w[0][i] * S.w[1][j] * S.w[2][k] *
-           (S.z[0] + S.z[1] * S.dk[0][i] + S.z[2] * S.dk[1][j] + S.z[3] * S.dk[2][k]);
+// MLS fit of the lattice values q over the 27 support points: a[0] the value
+// at the marker, a[1..3] the gradient in units of 1/h.  Separable sums: rows
+// along x, then y, then z (KZ: unroll count of the z planes; 1 keeps a
+// plane's nine gathers in flight at a time).
+// ld(i, j, k): the value at support point (i, j, k).
+template <int KZ, typename Load>
+__device__ __forceinline__ void mls_fit_with(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
+                                             double a[4], Load &&ld) {
+    double t0 = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll KZ
+    for (int k = 0; k < 3; ++k) {
+        double s0 = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double r0 = 0.0, rx = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double v = ld(i, j, k);
+                r0 += X.w[i] * v;
+                rx += X.e[i] * v;
+            }
+            s0 += Y.w[j] * r0;
+            sx += Y.w[j] * rx;
+            sy += Y.e[j] * r0;
+        }
+        t0 += Z.w[k] * s0;
+        tx += Z.w[k] * sx;
+        ty += Z.w[k] * sy;
+        tz += Z.e[k] * s0;
+    }
+    a[1] = tx;
+    a[2] = ty;
+    a[3] = tz;
+    a[0] = t0 - X.m * tx - Y.m * ty - Z.m * tz;
+}
+
+// The fit from a lattice field q in global memory (wrapped indices).
+template <typename R, int KZ = 3>
+__device__ __forceinline__ void mls_fit(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
+                                        const MlsGrid &g, const R *__restrict__ q, double a[4]) {
+    mls_fit_with<KZ>(X, Y, Z, a, [&](int i, int j, int k) {
+        return (double)q[(int64_t)Z.idx[k] * g.plane + (int64_t)Y.idx[j] * g.nx + X.idx[i]];
+    });
+}
+
+// sum_k phi_k (1 up to rounding: the fit reproduces constants).
+__device__ __forceinline__ double mls_phi_sum(const MlsAxis &X, const MlsAxis &Y,
+                                              const MlsAxis &Z) {
+    const double gx = X.w[0] + X.w[1] + X.w[2], gy = Y.w[0] + Y.w[1] + Y.w[2],
+                 gz = Z.w[0] + Z.w[1] + Z.w[2];
+    const double ex = X.e[0] + X.e[1] + X.e[2], ey = Y.e[0] + Y.e[1] + Y.e[2],
+                 ez = Z.e[0] + Z.e[1] + Z.e[2];
+    return gx * gy * gz - X.m * ex * gy * gz - Y.m * gx * ey * gz - Z.m * gx * gy * ez;
+}
+
+// fn(i, j, k, phi_ijk) at the 27 support points, in (k, j, i) order.
+template <typename Fn>
+__device__ __forceinline__ void mls_for_each_phi(const MlsAxis &X, const MlsAxis &Y,
+                                                 const MlsAxis &Z, Fn &&fn) {
+    double hx[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) hx[i] = X.m * X.e[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double hz = Z.m * Z.e[k];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double gyz = Y.w[j] * Z.w[k];
+            const double t = gyz - (Y.m * Y.e[j] * Z.w[k] + Y.w[j] * hz);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) fn(i, j, k, X.w[i] * t - hx[i] * gyz);
+        }
+    }
 }
 
 // Centroid and area of face f.
@@ -221,24 +252,18 @@ __global__ __launch_bounds__(256) void k_interp_mls(const double *__restrict__ X
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
-    MlsAxes M;
-    mls_axes(x, g, M);
+    MlsHalf H;
+    mls_half_axes(x, g, H);
     bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        MlsShape S;
-        bad |= !mls_shape(M, d, S);
-        const R *ud = u + d * g.field;
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const R *row = ud + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) acc += mls_phi(S, i, j, k) * (double)row[S.idx[0][i]];
-            }
-        U[3 * f + d] = (R)acc;
+        MlsAxis I;
+        mls_int_axis(x, d, g, I);
+        const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d), &AZ = axis_z(H, I, d);
+        bad |= !(AX.ok && AY.ok && AZ.ok);
+        double a[4];
+        mls_fit<R>(AX, AY, AZ, g, u + d * g.field, a);
+        U[3 * f + d] = (R)a[0];
     }
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
@@ -254,33 +279,25 @@ __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
-    MlsAxes M;
-    mls_axes(x, g, M);
+    MlsHalf H;
+    mls_half_axes(x, g, H);
     bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        MlsShape S;
-        bad |= !mls_shape(M, d, S);
-        // sum_k phi_k (1 up to rounding, since A z = e_0), as the paper writes c_l
-        double sphi = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) sphi += mls_phi(S, i, j, k);
+        MlsAxis I;
+        mls_int_axis(x, d, g, I);
+        const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d), &AZ = axis_z(H, I, d);
+        bad |= !(AX.ok && AY.ok && AZ.ok);
+        // c_l as the paper writes it, with sum_k phi_k (1 up to rounding)
+        const double sphi = mls_phi_sum(AX, AY, AZ);
         const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
         const double cl = area * hl / (sphi * g.h * g.h * g.h);
         const double Fd = (double)Fm[3 * f + d] * cl;
         R *fd = fld + d * g.field;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                R *row = fd + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) unsafeAtomicAdd(row + S.idx[0][i], (R)(mls_phi(S, i, j, k) * Fd));
-            }
+        mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
+            unsafeAtomicAdd(fd + (int64_t)AZ.idx[k] * g.plane + (int64_t)AY.idx[j] * g.nx + AX.idx[i],
+                            (R)(ph * Fd));
+        });
     }
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
@@ -296,70 +313,29 @@ __global__ __launch_bounds__(256) void k_direct_forcing_mls(
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
-    MlsAxes M;
-    mls_axes(x, g, M);
+    MlsHalf H;
+    mls_half_axes(x, g, H);
     bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        MlsShape S;
-        bad |= !mls_shape(M, d, S);
-        const R *ud = u + d * g.field;
-        double U = 0.0, sphi = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const R *row = ud + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const double ph = mls_phi(S, i, j, k);
-                    U += ph * (double)row[S.idx[0][i]];
-                    sphi += ph;
-                }
-            }
-        const double Fl = ((double)Vb[3 * f + d] - U) * inv_dt;
+        MlsAxis I;
+        mls_int_axis(x, d, g, I);
+        const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d), &AZ = axis_z(H, I, d);
+        bad |= !(AX.ok && AY.ok && AZ.ok);
+        double a[4];
+        mls_fit<R>(AX, AY, AZ, g, u + d * g.field, a);
+        const double Fl = ((double)Vb[3 * f + d] - a[0]) * inv_dt;
         if (Fout != nullptr) Fout[3 * f + d] = (R)Fl;
+        const double sphi = mls_phi_sum(AX, AY, AZ);
         const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
         const double Fd = Fl * area * hl / (sphi * g.h * g.h * g.h);
         R *fd = fld + d * g.field;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                R *row = fd + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) unsafeAtomicAdd(row + S.idx[0][i], (R)(mls_phi(S, i, j, k) * Fd));
-            }
+        mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
+            unsafeAtomicAdd(fd + (int64_t)AZ.idx[k] * g.plane + (int64_t)AY.idx[j] * g.nx + AX.idx[i],
+                            (R)(ph * Fd));
+        });
     }
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
-}
-
-// MLS fit about a point on one lattice, from its per-axis shape parts:
-// a = A^{-1} B q, the linear fit q ~ a0 + a1 dx + a2 dy + a3 dz (offsets in
-// units of h); a0 is the MLS value at the point and a1..a3 / h its gradient.
-// Returns false if the solve is not finite.
-template <typename R>
-__device__ __forceinline__ bool mls_fit(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
-                                        const MlsGrid &g, const R *__restrict__ q, double a[4]) {
-    // B q: weighted moments of the 27 values
-    double m[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const R *row = q + (int64_t)Z.idx[k] * g.plane + (int64_t)Y.idx[j] * g.nx;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double wq = X.w[i] * Y.w[j] * Z.w[k] * (double)row[X.idx[i]];
-                m[0] += wq;
-                m[1] += wq * X.dk[i];
-                m[2] += wq * Y.dk[j];
-                m[3] += wq * Z.dk[k];
-            }
-        }
-    MlsChol L;
-    mls_factor(X, Y, Z, L);
-    return mls_solve(L, m, a);
 }
 
 // External loads on face f from probes of length h along its unit normal:
@@ -368,7 +344,7 @@ __device__ __forceinline__ bool mls_fit(const MlsAxis &X, const MlsAxis &Y, cons
 // s h (Du/Dt).n, G_ij = du_i/dx_j (gradient of the MLS fit of lattice i),
 // tau = mu (G + G^T); the load is sum_s s (-p n + tau n) A.
 template <typename R>
-__global__ __launch_bounds__(256) void k_probe_loads(
+__global__ __launch_bounds__(256, 2) void k_probe_loads(
     const double *__restrict__ X, const int32_t *__restrict__ faces,
     const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
     const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
@@ -421,7 +397,8 @@ __global__ __launch_bounds__(256) void k_probe_loads(
             mls_axis(y.x, 0.5, g.nx, g, X);
             mls_axis(y.y, 0.5, g.ny, g, Y);
             mls_axis(y.z, 0.5, g.nz, g, Z);
-            bad |= !mls_fit<R>(X, Y, Z, g, pr, ap);
+            bad |= !(X.ok && Y.ok && Z.ok);
+            mls_fit<R, 1>(X, Y, Z, g, pr, ap);
         }
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {
@@ -430,7 +407,8 @@ __global__ __launch_bounds__(256) void k_probe_loads(
             mls_axis(y.x, mac_off(i, 0), g.nx, g, X);
             mls_axis(y.y, mac_off(i, 1), g.ny, g, Y);
             mls_axis(y.z, mac_off(i, 2), g.nz, g, Z);
-            bad |= !mls_fit<R>(X, Y, Z, g, u + i * g.field, ai);
+            bad |= !(X.ok && Y.ok && Z.ok);
+            mls_fit<R, 1>(X, Y, Z, g, u + i * g.field, ai);
             G[i][0] = ai[1] * g.inv_h;
             G[i][1] = ai[2] * g.inv_h;
             G[i][2] = ai[3] * g.inv_h;
@@ -459,7 +437,7 @@ __global__ __launch_bounds__(256) void k_probe_loads(
 // cell, as the fused step's tile uses): the supports of all three lattices lie
 // in points cell - 1 .. cell + 2 per axis.
 __device__ __forceinline__ int mls_cell(double x, double inv_h) {
-    double c = floor((x * inv_h - 0.5) + 0.5);      // the expression mls_shape uses
+    double c = floor((x * inv_h - 0.5) + 0.5);      // the expression mls_axis uses
     if (!(fabs(c) < 1.0e9)) c = 0.0;
     return (int)c;
 }
@@ -475,6 +453,7 @@ struct MlsUnitArgs {
     const void *Fm;          // marker forces (spreading)
     const void *u, *Vb;      // velocity field and desired marker velocity (direct forcing)
     void *Fout;              // marker forces written by direct forcing (may be NULL)
+    void *U;                 // interpolated marker velocities (interpolation)
     double inv_dt;
     void *f;
     MlsGrid g;
@@ -485,6 +464,172 @@ struct MlsUnitArgs {
     const uint16_t *frec_lid;
     int nmax, tile_bytes;
 };
+
+// Cell box (lo, hi per axis, reduced over the block) of the markers a unit
+// owns: the faces whose first corner is one of its owned nodes.
+template <int NT>
+__device__ __forceinline__ void owned_marker_box(const double *xs, const uint16_t *frec, int F,
+                                                 int N, double inv_h, int lo[3], int hi[3],
+                                                 int *ired, double *red) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = INT_MAX;
+        hi[c] = INT_MIN;
+    }
+    for (int t = threadIdx.x; t < F; t += NT) {
+        const uint16_t *q = frec + 4 * t;
+        if (q[0] >= N) continue;                   // first corner not owned here
+        const vec3<double> p = marker_of(xs, q);
+        const int cc[3] = {mls_cell(p.x, inv_h), mls_cell(p.y, inv_h), mls_cell(p.z, inv_h)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], cc[c]);
+            hi[c] = max(hi[c], cc[c]);
+        }
+    }
+    double none[1] = {0.0};
+    block_box_sums<NT, 1>(lo, hi, none, ired, red);
+}
+
+// Tile over grid points lo - 1 .. lo + L - 2 per axis (L = hi - lo + 4), the
+// threads' first points and strides (a tile no larger than the grid).
+template <int NT>
+__device__ __forceinline__ TileGeom mls_tile_geom(const int lo[3], int Tx, int Ty, int Tz,
+                                                  const MlsGrid &g) {
+    TileGeom tg{{lo[0], lo[1], lo[2]}, Tx, Ty, Tz, Tx * Ty * Tz, g.nx, g.ny, g.nz,
+                g.plane, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const int tid = threadIdx.x;
+    tg.g0[0] = wrapi(lo[0] - 1, g.nx);
+    tg.g0[1] = wrapi(lo[1] - 1, g.ny);
+    tg.g0[2] = wrapi(lo[2] - 1, g.nz);
+    const int qn = NT / Tx, r = tid / Tx;
+    tg.s[0] = NT % Tx;
+    tg.s[1] = qn % Ty;
+    tg.s[2] = qn / Ty;
+    tg.c0[0] = tid % Tx;
+    tg.c0[1] = r % Ty;
+    tg.c0[2] = r / Ty;
+    return tg;
+}
+
+// Interpolation at the faces owned by one work unit (one workgroup per unit).
+// The velocity over the cell box of the unit's markers is staged in LDS,
+// coalesced, so each marker's 81 reads come from LDS instead of scattered
+// gathers (one cache line per lane and read).  All three lattices are staged
+// at once when they fit, the marker then sharing its half-cell axes across
+// them; otherwise one lattice per pass; a unit whose box does not fit at all,
+// and any marker outside the box, gathers from u.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_interp_mls_units(MlsUnitArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ double red[NT / 64];
+    __shared__ int ired[6 * (NT / 64)];
+    const int tid = threadIdx.x;
+    const int w = blockIdx.x;
+    const int b = a.wu_body[w];
+    const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
+    const bool whole = nl1 == nl0;
+    const int64_t n0 = a.node_off[b];
+    const int NL = whole ? (int)(a.node_off[b + 1] - n0) : (int)(nl1 - nl0);
+    const int N = whole ? NL : a.wu_owned[w];
+    const int32_t *gid = a.wu_nodes + nl0;
+    const int64_t f0 = a.wu_foff[2 * w];
+    const int F = (int)(a.wu_foff[2 * w + 1] - f0);
+    if (NL == 0 || F == 0) return;     // uniform over the block
+    double *xs = (double *)lds;                                  // [nmax][3]
+    R *tile = (R *)(xs + 3 * a.nmax);                            // tile_bytes
+    const R *u = (const R *)a.u;
+    R *Uo = (R *)a.U;
+    const MlsGrid &g = a.g;
+    const uint16_t *frec = a.frec_lid + 4 * f0;
+
+    int lo[3], hi[3];
+    load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, g.inv_h, lo, hi);
+    owned_marker_box<NT>(xs, frec, F, N, g.inv_h, lo, hi, ired, red);
+    if (lo[0] > hi[0]) return;                     // no owned marker (uniform)
+    const long long Lx = (long long)hi[0] - lo[0] + 4, Ly = (long long)hi[1] - lo[1] + 4,
+                    Lz = (long long)hi[2] - lo[2] + 4;
+    const long long Tl = Lx * Ly * Lz;
+    const bool box_ok = Lx <= g.nx && Ly <= g.ny && Lz <= g.nz;
+    const int per_pass = !box_ok                                         ? 0
+                         : 3 * Tl * (long long)sizeof(R) <= a.tile_bytes ? 3
+                         : Tl * (long long)sizeof(R) <= a.tile_bytes     ? 1
+                                                                         : 0;
+    bool bad = false;
+    // marker t's fit on lattice d from the tile T of that lattice, or from u
+    // when a support point falls outside the tile
+    auto fit = [&](const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z, int d, const R *T,
+                   double out[4]) {
+        const int ox = X.c - lo[0], oy = Y.c - lo[1], oz = Z.c - lo[2];
+        if (T != nullptr && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Lx && oy + 2 < Ly &&
+            oz + 2 < Lz) {
+            const R *base = T + (oz * (int)Ly + oy) * (int)Lx + ox;
+            mls_fit_with<3>(X, Y, Z, out, [&](int i, int j, int k) {
+                return (double)base[(k * (int)Ly + j) * (int)Lx + i];
+            });
+        } else {
+            mls_fit<R>(X, Y, Z, g, u + d * g.field, out);
+        }
+    };
+    if (per_pass == 0) {
+        for (int t = tid; t < F; t += NT) {
+            const uint16_t *q = frec + 4 * t;
+            if (q[0] >= N) continue;
+            const vec3<double> x = marker_of(xs, q);
+            const int64_t pf = a.frec_perm[f0 + t];
+            MlsHalf H;
+            mls_half_axes(x, g, H);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                MlsAxis I;
+                mls_int_axis(x, d, g, I);
+                const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d), &AZ = axis_z(H, I, d);
+                bad |= !(AX.ok && AY.ok && AZ.ok);
+                double r[4];
+                mls_fit<R>(AX, AY, AZ, g, u + d * g.field, r);
+                Uo[3 * pf + d] = (R)r[0];
+            }
+        }
+    } else {
+        const TileGeom tg = mls_tile_geom<NT>(lo, (int)Lx, (int)Ly, (int)Lz, g);
+#pragma unroll 1
+        for (int d0 = 0; d0 < 3; d0 += per_pass) {
+            for (int l = 0; l < per_pass; ++l)
+                stage_tile<NT, R>(tile + l * Tl, u + (d0 + l) * g.field, tg);
+            lds_barrier();
+            for (int t = tid; t < F; t += NT) {
+                const uint16_t *q = frec + 4 * t;
+                if (q[0] >= N) continue;
+                const vec3<double> x = marker_of(xs, q);
+                const int64_t pf = a.frec_perm[f0 + t];
+                if (per_pass == 3) {
+                    MlsHalf H;
+                    mls_half_axes(x, g, H);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        MlsAxis I;
+                        mls_int_axis(x, d, g, I);
+                        const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d),
+                                      &AZ = axis_z(H, I, d);
+                        bad |= !(AX.ok && AY.ok && AZ.ok);
+                        double r[4];
+                        fit(AX, AY, AZ, d, tile + d * Tl, r);
+                        Uo[3 * pf + d] = (R)r[0];
+                    }
+                } else {
+                    MlsAxis AX, AY, AZ;
+                    mls_axes(x, d0, g, AX, AY, AZ);
+                    bad |= !(AX.ok && AY.ok && AZ.ok);
+                    double r[4];
+                    fit(AX, AY, AZ, d0, tile, r);
+                    Uo[3 * pf + d0] = (R)r[0];
+                }
+            }
+            lds_barrier();                         // before the next pass restages
+        }
+    }
+    if (bad) atomicOr(a.status, IP_STATUS_NONFINITE);
+}
 
 // Spreading of the faces owned by one work unit (one workgroup per unit).
 // DF (direct forcing): the marker force is F = (V^b - U) / dt with U
@@ -515,46 +660,16 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
 
     int lo[3], hi[3];
     load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, g.inv_h, lo, hi);
-    // cell box of the owned markers
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        lo[c] = INT_MAX;
-        hi[c] = INT_MIN;
-    }
-    for (int t = tid; t < F; t += NT) {
-        const uint16_t *q = a.frec_lid + 4 * (f0 + t);
-        if (q[0] >= N) continue;                   // first corner not owned here
-        const vec3<double> p = marker_of(xs, q);
-        const int cc[3] = {mls_cell(p.x, g.inv_h), mls_cell(p.y, g.inv_h), mls_cell(p.z, g.inv_h)};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = min(lo[c], cc[c]);
-            hi[c] = max(hi[c], cc[c]);
-        }
-    }
-    double none[1] = {0.0};
-    block_box_sums<NT, 1>(lo, hi, none, ired, red);
+    owned_marker_box<NT>(xs, a.frec_lid + 4 * f0, F, N, g.inv_h, lo, hi, ired, red);
     if (lo[0] > hi[0]) return;                     // no owned marker (uniform)
     // tile points lo - 1 .. hi + 2 per axis
     const long long Lx = (long long)hi[0] - lo[0] + 4, Ly = (long long)hi[1] - lo[1] + 4,
                     Lz = (long long)hi[2] - lo[2] + 4;
     const bool use_tile = Lx <= g.nx && Ly <= g.ny && Lz <= g.nz && Lx * Ly * Lz * 8 <= a.tile_bytes;
     const int Tx = use_tile ? (int)Lx : 1, Ty = use_tile ? (int)Ly : 1, Tz = use_tile ? (int)Lz : 1;
-    const long long Tl = (long long)Tx * Ty * Tz;
-    TileGeom tg{{lo[0], lo[1], lo[2]}, Tx, Ty, Tz, (int)(use_tile ? Tl : 0), g.nx, g.ny, g.nz,
-                g.plane, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    if (use_tile) {
-        tg.g0[0] = wrapi(lo[0] - 1, g.nx);
-        tg.g0[1] = wrapi(lo[1] - 1, g.ny);
-        tg.g0[2] = wrapi(lo[2] - 1, g.nz);
-        const int qn = NT / Tx, r = tid / Tx;
-        tg.s[0] = NT % Tx;
-        tg.s[1] = qn % Ty;
-        tg.s[2] = qn / Ty;
-        tg.c0[0] = tid % Tx;
-        tg.c0[1] = r % Ty;
-        tg.c0[2] = r / Ty;
-    }
+    TileGeom tg{{lo[0], lo[1], lo[2]}, 1, 1, 1, 0, g.nx, g.ny, g.nz, g.plane,
+                {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (use_tile) tg = mls_tile_geom<NT>(lo, Tx, Ty, Tz, g);
     bool bad = false;
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
@@ -570,31 +685,18 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
             const vec3<double> n = cross(xb - xa, xc - xa);
             const double area = 0.5 * sqrt(dot(n, n));
             const vec3<double> p = marker_of(xs, q);
-            MlsShape S;
-            bad |= !mls_shape(p, d, g, S);
-            double sphi = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) sphi += mls_phi(S, i, j, k);
+            MlsAxis AX, AY, AZ;
+            mls_axes(p, d, g, AX, AY, AZ);
+            bad |= !(AX.ok && AY.ok && AZ.ok);
+            const double sphi = mls_phi_sum(AX, AY, AZ);
             const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
             const double cl = area * hl / (sphi * g.h * g.h * g.h);
             const int64_t pf = a.frec_perm[f0 + t];
             double Fl;
             if constexpr (DF) {
-                const R *ud = (const R *)a.u + d * g.field;
-                double U = 0.0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const R *row = ud + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) U += mls_phi(S, i, j, k) * (double)row[S.idx[0][i]];
-                    }
-                Fl = ((double)((const R *)a.Vb)[3 * pf + d] - U) * a.inv_dt;
+                double fit[4];
+                mls_fit<R>(AX, AY, AZ, g, (const R *)a.u + d * g.field, fit);
+                Fl = ((double)((const R *)a.Vb)[3 * pf + d] - fit[0]) * a.inv_dt;
                 if (a.Fout != nullptr) ((R *)a.Fout)[3 * pf + d] = (R)Fl;
             } else {
                 Fl = (double)Fm[3 * pf + d];
@@ -602,28 +704,20 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
             const double Fd = Fl * cl;
             // support point c - 1 + j is tile point c + j - lo (inside the tile
             // for every marker the box was taken from; checked all the same)
-            const int ox = S.c[0] - lo[0], oy = S.c[1] - lo[1], oz = S.c[2] - lo[2];
+            const int ox = AX.c - lo[0], oy = AY.c - lo[1], oz = AZ.c - lo[2];
             const bool in_tile = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Tx &&
                                  oy + 2 < Ty && oz + 2 < Tz;
             if (in_tile) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i)
-                            lds_add(tile + ((oz + k) * Ty + (oy + j)) * Tx + (ox + i),
-                                    mls_phi(S, i, j, k) * Fd);
+                double *base = tile + (oz * Ty + oy) * Tx + ox;
+                mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
+                    lds_add(base + (k * Ty + j) * Tx + i, ph * Fd);
+                });
             } else {
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        R *row = fd + (int64_t)S.idx[2][k] * g.plane + (int64_t)S.idx[1][j] * g.nx;
-#pragma unroll
-                        for (int i = 0; i < 3; ++i)
-                            unsafeAtomicAdd(row + S.idx[0][i], (R)(mls_phi(S, i, j, k) * Fd));
-                    }
+                mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
+                    unsafeAtomicAdd(fd + (int64_t)AZ.idx[k] * g.plane + (int64_t)AY.idx[j] * g.nx +
+                                        AX.idx[i],
+                                    (R)(ph * Fd));
+                });
             }
         }
         if (use_tile) {
@@ -681,6 +775,7 @@ MlsGrid mls_grid(const ip_plan *p, double alpha) {
     // stay far inside the double range; beyond, each weight takes its own
     // exponential
     g.fast = g.q2 <= 200.0 ? 1 : 0;
+
     return g;
 }
 
@@ -711,13 +806,16 @@ static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArg
 // One workgroup per unit fills the LDS with its tile, so the workgroup size
 // sets the waves per SIMD: 768 threads give 3 (512 gave 2 and were slower).
 constexpr int kMlsThreads = 768;
+// Interpolation on work units: the tile is read, not added to.
+constexpr int kMlsInterpThreads = 768;
 
 // Launch attributes of the per-unit kernels (their dynamic LDS), set once when
 // the plan is built, so that the launches themselves can be captured.
 template <typename R>
 static ip_status set_unit_attributes(size_t lds) {
-    const void *fns[2] = {(const void *)k_spread_mls_units<R, kMlsThreads, false>,
-                          (const void *)k_spread_mls_units<R, kMlsThreads, true>};
+    const void *fns[3] = {(const void *)k_spread_mls_units<R, kMlsThreads, false>,
+                          (const void *)k_spread_mls_units<R, kMlsThreads, true>,
+                          (const void *)k_interp_mls_units<R, kMlsInterpThreads>};
     for (const void *fn : fns)
         IP_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return IP_OK;
@@ -735,6 +833,21 @@ ip_status launch_interp_mls(ip_plan *p, const double *X, const void *u, double a
                             hipStream_t s) {
     if (p->F == 0) return IP_OK;
     const MlsGrid g = mls_grid(p, alpha);
+    if (p->fused_all && p->n_units > 0) {
+        MlsUnitArgs a{};
+        size_t lds = 0;
+        IP_TRY(unit_args(p, X, alpha, a, lds));
+        a.u = u;
+        a.U = U;
+        if (p->prec == IP_F64)
+            hipLaunchKernelGGL((k_interp_mls_units<double, kMlsInterpThreads>), dim3(p->n_units),
+                               dim3(kMlsInterpThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_interp_mls_units<float, kMlsInterpThreads>), dim3(p->n_units),
+                               dim3(kMlsInterpThreads), lds, s, a);
+        IP_HIP_CHECK(hipGetLastError());
+        return IP_OK;
+    }
     const dim3 grid(nblocks(p->F, 256)), block(256);
     if (p->prec == IP_F64)
         hipLaunchKernelGGL(k_interp_mls<double>, grid, block, 0, s, X, p->faces, p->F,

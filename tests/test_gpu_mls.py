@@ -18,6 +18,21 @@ from test_gpu_unfused import sheet_and_drop
 
 pytestmark = pytest.mark.gpu
 
+
+def wrapped_drops():
+    """Two level-2 drops on a 32^3 grid: one centred on a corner of the
+    periodic box (its supports wrap on every axis), one more than a box length
+    outside the box on every axis (its cells wrap from beyond the grid)."""
+    v, f = W.icosphere(2)
+    rng = np.random.default_rng(41)
+    bodies = []
+    for c in ([0.0, 0.0, 0.0], [1.6, -1.3, 2.3]):
+        Xref = np.array(c) + 0.08 * v
+        X = Xref + rng.normal(0, 0.001, size=v.shape)
+        bodies.append(dict(X=X, Xref=Xref, faces=f, closed=True))
+    return W._assemble(bodies, "wrapped_drops", W.Grid(32, 32, 32, 1.0 / 32), 1e-3, 1, "f64",
+                       (1.0, 0.01, 0.1, 1.0))
+
 CASES = {
     "drop_L3_64": lambda: W.config0(),
     "four_L4_128": lambda: W.small_suspension(4, 4, 128, r=0.04),
@@ -31,6 +46,7 @@ CASES = {
     # a plan without fused work units: spreading and direct forcing take the
     # per-marker kernels with device atomics
     "unfused_sheet_drop": sheet_and_drop,
+    "wrapped_drops": wrapped_drops,
 }
 
 
