@@ -59,7 +59,8 @@ void free_plan(ip_plan *p) {
     void *ptrs[] = {p->node_off, p->edge_off, p->face_off, p->faces, p->edges4, p->closed,
                     p->pinned, p->csr_ptr, p->csr_slot, p->slots, p->Fbuf, p->Ubuf,
                     p->Vbuf, p->Abuf, p->status, p->bwd_dots, p->bref_l0, p->bref_cs0,
-                    p->bref_A0, p->bref_V0, p->wu_body, p->wu_owned, p->wu_noff, p->wu_nodes,
+                    p->bref_A0, p->bref_V0, p->wu_body, p->wu_owned, p->wu_pinned, p->wu_noff,
+                    p->wu_nodes,
                     p->wu_eoff, p->wu_foff, p->erec_perm, p->erec_lid, p->frec_perm,
                     p->frec_lid, p->edge_rec, p->face_rec, p->patched_bodies,
                     p->patched_units, p->Xstage, p->ew_store, p->ew_rec_store, p->ew_bad};
@@ -231,6 +232,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
             // ranges as (begin, end) pairs: units are stored largest first,
             // their lists in build order
             std::vector<int32_t> body(W), owned(W), pb, pu;
+            std::vector<uint8_t> upin(W, 0);
             std::vector<int64_t> n2(2 * W), e2(2 * W), f2(2 * W);
             std::vector<char> patched(B, 0);
             for (int w = 0; w < W; ++w) {
@@ -244,6 +246,12 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
                 f2[2 * w] = u.face_begin;
                 f2[2 * w + 1] = u.face_end;
                 if (u.node_end > u.node_begin) {
+                    for (int64_t i = u.node_begin; i < u.node_end; ++i) upin[w] |= pin[wu.nodes[i]];
+                } else {
+                    for (int64_t i = m->node_off[u.body]; i < m->node_off[u.body + 1]; ++i)
+                        upin[w] |= pin[i];
+                }
+                if (u.node_end > u.node_begin) {
                     pu.push_back(w);
                     if (!patched[u.body]) pb.push_back(u.body);
                     patched[u.body] = 1;
@@ -251,6 +259,7 @@ ip_status build_plan(ip_plan *p, const ip_mesh *m, const ip_grid *grid, ip_preci
             }
             IP_TRY(upload(&p->wu_body, body.data(), W));
             IP_TRY(upload(&p->wu_owned, owned.data(), W));
+            IP_TRY(upload(&p->wu_pinned, upin.data(), W));
             IP_TRY(upload(&p->wu_noff, n2.data(), 2 * W));
             IP_TRY(upload(&p->wu_eoff, e2.data(), 2 * W));
             IP_TRY(upload(&p->wu_foff, f2.data(), 2 * W));

@@ -82,6 +82,7 @@ struct ip_plan {
     int32_t n_units = 0;
     int32_t *wu_body = nullptr;   // [n_units] body of each unit, largest unit first
     int32_t *wu_owned = nullptr;  // [n_units] owned nodes
+    uint8_t *wu_pinned = nullptr; // [n_units] 1 = some node of the unit is pinned
     int64_t *wu_noff = nullptr;   // [n_units][2] node-list range (empty: whole body)
     int32_t *wu_nodes = nullptr;  // global ids of patch nodes, owned first
     int64_t *wu_eoff = nullptr;   // [n_units][2] edge-record range

@@ -455,6 +455,7 @@ struct VjpArgs {
     const double *Vpre, *dVpre;   // patched bodies: volume and its tangent
     uint32_t *status;
     const int32_t *wu_body, *wu_owned, *wu_nodes;
+    const uint8_t *wu_pinned;     // [n_units] some node of the unit pinned
     const int64_t *wu_noff, *wu_eoff, *wu_foff;
     const void *erec, *frec;
     const double *ew;             // [n_erec][2] per-edge weights on ks, kb (EW only)
@@ -495,9 +496,11 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArg
     bool bad = false;
     const double c2 = a.dt * a.dt / a.mass[b];
     const auto gnode = [&](int l) -> int64_t { return whole ? n0 + l : (int64_t)gid[l]; };
+    // units without pinned nodes skip the flag's load in every tangent
+    const bool any_pin = a.wu_pinned[w] != 0;
     const auto tangent = [&](int l) -> vec3<double> {   // P of unit node l
         const int64_t g = gnode(l);
-        if (a.pinned[g]) return {0.0, 0.0, 0.0};
+        if (any_pin && a.pinned[g]) return {0.0, 0.0, 0.0};
         return {a.lam_in[3 * g], a.lam_in[3 * g + 1], a.lam_in[3 * g + 2]};
     };
     const auto dualx = [&](int l, const vec3<double> &t) -> vec3<dual> {
@@ -507,6 +510,13 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArg
         lds_add(dF + 3 * l, k * v.x.d);
         lds_add(dF + 3 * l + 1, k * v.y.d);
         lds_add(dF + 3 * l + 2, k * v.z.d);
+    };
+    // k1 v1 + k2 v2 in one addition per component
+    const auto addd2 = [&](int l, double k1, const vec3<dual> &v1, double k2,
+                           const vec3<dual> &v2) {
+        lds_add(dF + 3 * l, k1 * v1.x.d + k2 * v2.x.d);
+        lds_add(dF + 3 * l + 1, k1 * v1.y.d + k2 * v2.y.d);
+        lds_add(dF + 3 * l + 2, k1 * v1.z.d + k2 * v2.z.d);
     };
 
     int fi[FK][3];
@@ -539,11 +549,12 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArg
 #pragma unroll
         for (int s = 0; s < FK; ++s) {
             if (fmask & (1u << s)) {
-                dual v;
-                double ar;
-                face_geometry<dual, double>(dualx(fi[s][0], tangent(fi[s][0])),
-                                            dualx(fi[s][1], tangent(fi[s][1])),
-                                            dualx(fi[s][2], tangent(fi[s][2])), anchor, v, ar);
+                // 6 V contribution of the face about the anchor (the area is
+                // not needed here)
+                const vec3<dual> xi = dualx(fi[s][0], tangent(fi[s][0])) - anchor,
+                                 xj = dualx(fi[s][1], tangent(fi[s][1])) - anchor,
+                                 xk = dualx(fi[s][2], tangent(fi[s][2])) - anchor;
+                const dual v = dot(xi, cross(xj, xk));
                 sums[0] += v.v;
                 sums[1] += v.d;
             }
@@ -572,12 +583,9 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArg
                 vec3<dual> gi, gj, gk, gv;
                 bad |= face_parts<dual, dual>(dualx(i, pi), dualx(j, pj), dualx(k, pk),
                                               dual(fa0[s]), 1.0, sV1, gi, gj, gk, gv);
-                addd(i, kA, gi);
-                addd(j, kA, gj);
-                addd(k, kA, gk);
-                addd(i, kV, gv);
-                addd(j, kV, gv);
-                addd(k, kV, gv);
+                addd2(i, kA, gi, kV, gv);
+                addd2(j, kA, gj, kV, gv);
+                addd2(k, kA, gk, kV, gv);
                 if (whole || i < N) {
                     dot_a += gi.x.v * pi.x + gi.y.v * pi.y + gi.z.v * pi.z + gj.x.v * pj.x +
                              gj.y.v * pj.y + gj.z.v * pj.z + gk.x.v * pk.x + gk.y.v * pk.y +
@@ -607,13 +615,14 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArg
                 wb = wt.y;
             }
             const double kse = ks * ws, kbe = kb * wb;
-            addd(q.x, kse, fsp);
-            addd(q.y, -kse, fsp);
             if (hinge) {
-                addd(q.x, kbe, h1);
-                addd(q.y, kbe, h2);
+                addd2(q.x, kse, fsp, kbe, h1);
+                addd2(q.y, -kse, fsp, kbe, h2);
                 addd(q.z, kbe, h3);
                 addd(q.w, kbe, h4);
+            } else {
+                addd(q.x, kse, fsp);
+                addd(q.y, -kse, fsp);
             }
             if (whole || q.x < N) {
                 dot_s += ws * (fsp.x.v * (p1.x - p2.x) + fsp.y.v * (p1.y - p2.y) +
@@ -939,6 +948,7 @@ ip_status launch_step_vjp_fused(ip_plan *p, const double *X, const ip_reference 
     a.status = p->status;
     a.wu_body = p->wu_body;
     a.wu_owned = p->wu_owned;
+    a.wu_pinned = p->wu_pinned;
     a.wu_nodes = p->wu_nodes;
     a.wu_noff = p->wu_noff;
     a.wu_eoff = p->wu_eoff;
