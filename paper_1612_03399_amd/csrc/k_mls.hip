@@ -160,6 +160,13 @@ __device__ __forceinline__ void mls_axes(const vec3<double> &x, int d, const Mls
 // at the marker, a[1..3] the gradient in units of 1/h.  Separable sums: rows
 // along x, then y, then z (KZ: unroll count of the z planes; 1 keeps a
 // plane's nine gathers in flight at a time).
+// a[k] by selects: with k a loop counter that is not unrolled, indexing the
+// array would place it in scratch memory
+template <typename T>
+__device__ __forceinline__ T pick3(const T (&a)[3], int k) {
+    return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+
 // ld(i, j, k): the value at support point (i, j, k).
 template <int KZ, typename Load>
 __device__ __forceinline__ void mls_fit_with(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
@@ -181,10 +188,12 @@ __device__ __forceinline__ void mls_fit_with(const MlsAxis &X, const MlsAxis &Y,
             sx += Y.w[j] * rx;
             sy += Y.e[j] * r0;
         }
-        t0 += Z.w[k] * s0;
-        tx += Z.w[k] * sx;
-        ty += Z.w[k] * sy;
-        tz += Z.e[k] * s0;
+        const double wz = KZ == 1 ? pick3(Z.w, k) : Z.w[k];
+        const double ez = KZ == 1 ? pick3(Z.e, k) : Z.e[k];
+        t0 += wz * s0;
+        tx += wz * sx;
+        ty += wz * sy;
+        tz += ez * s0;
     }
     a[1] = tx;
     a[2] = ty;
@@ -197,7 +206,8 @@ template <typename R, int KZ = 3>
 __device__ __forceinline__ void mls_fit(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
                                         const MlsGrid &g, const R *__restrict__ q, double a[4]) {
     mls_fit_with<KZ>(X, Y, Z, a, [&](int i, int j, int k) {
-        return (double)q[(int64_t)Z.idx[k] * g.plane + (int64_t)Y.idx[j] * g.nx + X.idx[i]];
+        const int zk = KZ == 1 ? pick3(Z.idx, k) : Z.idx[k];
+        return (double)q[(int64_t)zk * g.plane + (int64_t)Y.idx[j] * g.nx + X.idx[i]];
     });
 }
 
@@ -231,6 +241,25 @@ __device__ __forceinline__ void mls_for_each_phi(const MlsAxis &X, const MlsAxis
     }
 }
 
+// out[3 f + c] = v[c] for the wave's consecutive faces f = f0 + lane (those
+// below F), written as whole rows: lane l stores elements l, l + 64 and
+// l + 128 of the wave's 192-value segment, exchanged across lanes, so each
+// store instruction covers consecutive words rather than every third one (a
+// stride-3 store leaves partial lines).  f0 is the face of lane 0; every lane
+// of the wave calls it.
+template <typename R>
+__device__ __forceinline__ void store3_rows(R *__restrict__ out, int64_t f0, int64_t F,
+                                            const double v[3]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int e = lane + 64 * k, src = e / 3, c = e - 3 * src;
+        const double a0 = __shfl(v[0], src), a1 = __shfl(v[1], src), a2 = __shfl(v[2], src);
+        const double val = c == 0 ? a0 : (c == 1 ? a1 : a2);
+        if (f0 + src < F) out[3 * f0 + e] = (R)val;
+    }
+}
+
 // Centroid and area of face f.
 __device__ __forceinline__ vec3<double> centroid(const double *X, const int32_t *faces, int64_t f,
                                                  double &area) {
@@ -250,11 +279,11 @@ __global__ __launch_bounds__(256) void k_interp_mls(const double *__restrict__ X
                                                     R *__restrict__ U, uint32_t *status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
+    bool bad = false;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
     MlsHalf H;
     mls_half_axes(x, g, H);
-    bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         MlsAxis I;
@@ -344,13 +373,11 @@ __global__ __launch_bounds__(256) void k_direct_forcing_mls(
 // s h (Du/Dt).n, G_ij = du_i/dx_j (gradient of the MLS fit of lattice i),
 // tau = mu (G + G^T); the load is sum_s s (-p n + tau n) A.
 template <typename R>
-__global__ __launch_bounds__(256, 2) void k_probe_loads(
-    const double *__restrict__ X, const int32_t *__restrict__ faces,
-    const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
-    const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
-    double mu, R *__restrict__ Fext, uint32_t *status) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= F) return;
+__device__ __forceinline__ void probe_face(
+    int64_t f, const double *__restrict__ X, const int32_t *__restrict__ faces,
+    const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B,
+    const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, const MlsGrid &g,
+    double mu, double out[3], uint32_t *status) {
     // body of face f: the last b with face_off[b] <= f
     int lo = 0, hi = B - 1;
     while (lo < hi) {
@@ -366,9 +393,7 @@ __global__ __launch_bounds__(256, 2) void k_probe_loads(
     const double nlen = sqrt(dot(nn, nn));
     if (!(nlen > 0.0)) {
         // a zero-area face has no normal: no probe, no load
-        Fext[3 * f] = (R)0.0;
-        Fext[3 * f + 1] = (R)0.0;
-        Fext[3 * f + 2] = (R)0.0;
+        out[0] = out[1] = out[2] = 0.0;
         atomicOr(status, nlen == 0.0 ? IP_STATUS_DEGENERATE : IP_STATUS_NONFINITE);
         return;
     }
@@ -391,7 +416,7 @@ __global__ __launch_bounds__(256, 2) void k_probe_loads(
         // each fit computes its own axes: their exponentials overlap that
         // fit's 27 gathers (sharing the half-cell axes across the four fits
         // leaves the gathers exposed and measured slower)
-        double ap[4], G[3][3];
+        double ap[4];
         {
             MlsAxis X, Y, Z;
             mls_axis(y.x, 0.5, g.nx, g, X);
@@ -400,6 +425,11 @@ __global__ __launch_bounds__(256, 2) void k_probe_loads(
             bad |= !(X.ok && Y.ok && Z.ok);
             mls_fit<R, 1>(X, Y, Z, g, pr, ap);
         }
+        // (G + G^T) n, accumulated row by row as the fits give the rows
+        // G_i. of the velocity gradient: component i takes (G n)_i, every
+        // component j takes G_ij n_i (no array indexed by i, which would
+        // live in scratch memory)
+        double tn0 = 0.0, tn1 = 0.0, tn2 = 0.0;
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {
             double ai[4];
@@ -409,28 +439,37 @@ __global__ __launch_bounds__(256, 2) void k_probe_loads(
             mls_axis(y.z, mac_off(i, 2), g.nz, g, Z);
             bad |= !(X.ok && Y.ok && Z.ok);
             mls_fit<R, 1>(X, Y, Z, g, u + i * g.field, ai);
-            G[i][0] = ai[1] * g.inv_h;
-            G[i][1] = ai[2] * g.inv_h;
-            G[i][2] = ai[3] * g.inv_h;
+            const double gx = ai[1] * g.inv_h, gy = ai[2] * g.inv_h, gz = ai[3] * g.inv_h;
+            const double ni = i == 0 ? nu.x : (i == 1 ? nu.y : nu.z);
+            const double gn = gx * nu.x + gy * nu.y + gz * nu.z;
+            tn0 += gx * ni + (i == 0 ? gn : 0.0);
+            tn1 += gy * ni + (i == 1 ? gn : 0.0);
+            tn2 += gz * ni + (i == 2 ? gn : 0.0);
         }
         const double pl = ap[0] + sg * g.h * an;
-        const double n3[3] = {nu.x, nu.y, nu.z};
-        double Fs[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            double tn = 0.0;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) tn += mu * (G[i][j] + G[j][i]) * n3[j];
-            Fs[i] = sg * (-pl * n3[i] + tn) * area;
-        }
+        const double Fs[3] = {sg * (-pl * nu.x + mu * tn0) * area,
+                              sg * (-pl * nu.y + mu * tn1) * area,
+                              sg * (-pl * nu.z + mu * tn2) * area};
         F0 += Fs[0];
         F1 += Fs[1];
         F2 += Fs[2];
     }
-    Fext[3 * f] = (R)F0;
-    Fext[3 * f + 1] = (R)F1;
-    Fext[3 * f + 2] = (R)F2;
+    out[0] = F0;
+    out[1] = F1;
+    out[2] = F2;
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256, 2) void k_probe_loads(
+    const double *__restrict__ X, const int32_t *__restrict__ faces,
+    const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
+    const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
+    double mu, R *__restrict__ Fext, uint32_t *status) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (f < F) probe_face<R>(f, X, faces, face_off, closed, B, u, pr, acc, g, mu, v, status);
+    store3_rows(Fext, f - (threadIdx.x & 63), F, v);
 }
 
 // The centroid's cell (the stencil centre of the lattices staggered by half a
@@ -448,6 +487,12 @@ __device__ __forceinline__ vec3<double> marker_of(const double *xs, const uint16
     return vec3<double>{s.x * (1.0 / 3.0), s.y * (1.0 / 3.0), s.z * (1.0 / 3.0)};
 }
 
+// Centroid of the face with unit-local corners c (positions in LDS).
+__device__ __forceinline__ vec3<double> marker_at(const double *xs, const int c[3]) {
+    const vec3<double> s = ldx(xs, c[0]) + ldx(xs, c[1]) + ldx(xs, c[2]);
+    return vec3<double>{s.x * (1.0 / 3.0), s.y * (1.0 / 3.0), s.z * (1.0 / 3.0)};
+}
+
 struct MlsUnitArgs {
     const double *X;
     const void *Fm;          // marker forces (spreading)
@@ -462,8 +507,31 @@ struct MlsUnitArgs {
     const int32_t *wu_body, *wu_owned, *wu_nodes, *frec_perm;
     const int64_t *wu_noff, *wu_foff;
     const uint16_t *frec_lid;
+    const int32_t *faces;        // [F][3] global corners (whole units take faces in face order)
+    const int64_t *face_off;
     int nmax, tile_bytes;
 };
+
+// The unit's t-th face: unit-local corners c and the global face id, or -1
+// for a patch's record whose first corner it does not own.  A whole unit
+// (fb = its body's first face) takes its faces in face order, so that
+// consecutive lanes read and write consecutive faces; a patch takes its
+// records.
+__device__ __forceinline__ int64_t unit_face(const MlsUnitArgs &a, bool whole, int64_t fb,
+                                             int64_t n0, int64_t f0, int N, int t, int c[3]) {
+    if (whole) {
+        const int32_t *q = a.faces + 3 * (fb + t);
+        c[0] = (int)(q[0] - n0);
+        c[1] = (int)(q[1] - n0);
+        c[2] = (int)(q[2] - n0);
+        return fb + t;
+    }
+    const uint16_t *q = a.frec_lid + 4 * (f0 + t);
+    c[0] = q[0];
+    c[1] = q[1];
+    c[2] = q[2];
+    return c[0] < N ? (int64_t)a.frec_perm[f0 + t] : -1;
+}
 
 // Cell box (lo, hi per axis, reduced over the block) of the markers a unit
 // owns: the faces whose first corner is one of its owned nodes.
@@ -571,59 +639,66 @@ __global__ __launch_bounds__(NT) void k_interp_mls_units(MlsUnitArgs a) {
             mls_fit<R>(X, Y, Z, g, u + d * g.field, out);
         }
     };
-    if (per_pass == 0) {
-        for (int t = tid; t < F; t += NT) {
-            const uint16_t *q = frec + 4 * t;
-            if (q[0] >= N) continue;
-            const vec3<double> x = marker_of(xs, q);
-            const int64_t pf = a.frec_perm[f0 + t];
+    // whole units take their faces in face order: rows of U written whole
+    const int64_t fb = whole ? a.face_off[b] : 0;
+    const auto face_of = [&](int t, int c[3]) -> int64_t {
+        return unit_face(a, whole, fb, n0, f0, N, t, c);
+    };
+    const int lane = tid & 63;
+    if (per_pass != 1) {
+        // all three lattices per marker, from the tile (per_pass 3) or from u
+        if (per_pass == 3) {
+            const TileGeom tg = mls_tile_geom<NT>(lo, (int)Lx, (int)Ly, (int)Lz, g);
+            for (int l = 0; l < 3; ++l) stage_tile<NT, R>(tile + l * Tl, u + l * g.field, tg);
+            lds_barrier();
+        }
+        for (int t0 = tid - lane; t0 < F; t0 += NT) {          // wave-uniform bound
+            // lanes past the last face repeat it (every lane takes part in
+            // the row store); a patch's records it does not own are computed
+            // and not stored
+            const int t = min(t0 + lane, F - 1);
+            int c[3];
+            const int64_t pf = face_of(t, c);
+            const vec3<double> x = marker_at(xs, c);
             MlsHalf H;
             mls_half_axes(x, g, H);
+            double v[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 MlsAxis I;
                 mls_int_axis(x, d, g, I);
                 const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d), &AZ = axis_z(H, I, d);
-                bad |= !(AX.ok && AY.ok && AZ.ok);
+                if (pf >= 0) bad |= !(AX.ok && AY.ok && AZ.ok);
                 double r[4];
-                mls_fit<R>(AX, AY, AZ, g, u + d * g.field, r);
-                Uo[3 * pf + d] = (R)r[0];
+                fit(AX, AY, AZ, d, per_pass == 3 ? tile + d * Tl : nullptr, r);
+                v[d] = r[0];
+            }
+            if (whole) {
+                store3_rows(Uo, fb + t0, fb + F, v);
+            } else if (pf >= 0 && t0 + lane < F) {
+                Uo[3 * pf] = (R)v[0];
+                Uo[3 * pf + 1] = (R)v[1];
+                Uo[3 * pf + 2] = (R)v[2];
             }
         }
     } else {
+        // one lattice per pass
         const TileGeom tg = mls_tile_geom<NT>(lo, (int)Lx, (int)Ly, (int)Lz, g);
 #pragma unroll 1
-        for (int d0 = 0; d0 < 3; d0 += per_pass) {
-            for (int l = 0; l < per_pass; ++l)
-                stage_tile<NT, R>(tile + l * Tl, u + (d0 + l) * g.field, tg);
+        for (int d0 = 0; d0 < 3; ++d0) {
+            stage_tile<NT, R>(tile, u + d0 * g.field, tg);
             lds_barrier();
             for (int t = tid; t < F; t += NT) {
-                const uint16_t *q = frec + 4 * t;
-                if (q[0] >= N) continue;
-                const vec3<double> x = marker_of(xs, q);
-                const int64_t pf = a.frec_perm[f0 + t];
-                if (per_pass == 3) {
-                    MlsHalf H;
-                    mls_half_axes(x, g, H);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        MlsAxis I;
-                        mls_int_axis(x, d, g, I);
-                        const MlsAxis &AX = axis_x(H, I, d), &AY = axis_y(H, I, d),
-                                      &AZ = axis_z(H, I, d);
-                        bad |= !(AX.ok && AY.ok && AZ.ok);
-                        double r[4];
-                        fit(AX, AY, AZ, d, tile + d * Tl, r);
-                        Uo[3 * pf + d] = (R)r[0];
-                    }
-                } else {
-                    MlsAxis AX, AY, AZ;
-                    mls_axes(x, d0, g, AX, AY, AZ);
-                    bad |= !(AX.ok && AY.ok && AZ.ok);
-                    double r[4];
-                    fit(AX, AY, AZ, d0, tile, r);
-                    Uo[3 * pf + d0] = (R)r[0];
-                }
+                int c[3];
+                const int64_t pf = face_of(t, c);
+                if (pf < 0) continue;
+                const vec3<double> x = marker_at(xs, c);
+                MlsAxis AX, AY, AZ;
+                mls_axes(x, d0, g, AX, AY, AZ);
+                bad |= !(AX.ok && AY.ok && AZ.ok);
+                double r[4];
+                fit(AX, AY, AZ, d0, tile, r);
+                Uo[3 * pf + d0] = (R)r[0];
             }
             lds_barrier();                         // before the next pass restages
         }
@@ -679,19 +754,23 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
             lds_barrier();
         }
         for (int t = tid; t < F; t += NT) {
-            const uint16_t *q = a.frec_lid + 4 * (f0 + t);
-            if (q[0] >= N) continue;
+            // record order also for whole units: the records of a run of 64
+            // touch distinct nodes, so the lanes of a wave add into distinct
+            // tile points (in face order neighbouring faces of the subdivided
+            // mesh collide: 1.30 against 0.72 ms on the 1000-drop batch)
+            int q[3];
+            const int64_t pf = unit_face(a, false, 0, n0, f0, N, t, q);
+            if (pf < 0) continue;
             const vec3<double> xa = ldx(xs, q[0]), xb = ldx(xs, q[1]), xc = ldx(xs, q[2]);
             const vec3<double> n = cross(xb - xa, xc - xa);
             const double area = 0.5 * sqrt(dot(n, n));
-            const vec3<double> p = marker_of(xs, q);
+            const vec3<double> p = marker_at(xs, q);
             MlsAxis AX, AY, AZ;
             mls_axes(p, d, g, AX, AY, AZ);
             bad |= !(AX.ok && AY.ok && AZ.ok);
             const double sphi = mls_phi_sum(AX, AY, AZ);
             const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
             const double cl = area * hl / (sphi * g.h * g.h * g.h);
-            const int64_t pf = a.frec_perm[f0 + t];
             double Fl;
             if constexpr (DF) {
                 double fit[4];
@@ -797,6 +876,8 @@ static ip_status unit_args(ip_plan *p, const double *X, double alpha, MlsUnitArg
     a.wu_noff = p->wu_noff;
     a.wu_foff = p->wu_foff;
     a.frec_lid = p->frec_lid;
+    a.faces = p->faces;
+    a.face_off = p->face_off;
     a.nmax = p->fused_nmax;
     a.tile_bytes = (int)std::max<long long>((lds_optin - 1024 - 24LL * a.nmax) / 16 * 16, 0);
     lds = (size_t)24 * a.nmax + (size_t)a.tile_bytes;
