@@ -61,7 +61,6 @@ struct MlsAxis {
     double w[3];         // weights, normalised to sum one
     double e[3];         // gradient weights w_j (d_j - m) / v
     double m;            // mean offset sum_j w_j d_j (offsets d_j = (x^k - x) / h)
-    int idx[3];          // wrapped lattice indices
     int c;               // unwrapped index of the middle point
     bool ok;             // weights and variance finite, variance positive
 };
@@ -74,10 +73,6 @@ __device__ __forceinline__ void mls_axis(double xa, double off, int n, const Mls
     double dk[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) dk[j] = (c - 1.0 + j) - s;
-    const int m = wrapi((int)c, n);
-    A.idx[0] = m == 0 ? n - 1 : m - 1;
-    A.idx[1] = m;
-    A.idx[2] = m == n - 1 ? 0 : m + 1;
     A.c = (int)c;
     double w0, w1, w2;
     if (g.fast) {
@@ -160,6 +155,17 @@ __device__ __forceinline__ void mls_axes(const vec3<double> &x, int d, const Mls
 // at the marker, a[1..3] the gradient in units of 1/h.  Separable sums: rows
 // along x, then y, then z (KZ: unroll count of the z planes; 1 keeps a
 // plane's nine gathers in flight at a time).
+// Wrapped lattice indices of an axis's three support points (c - 1, c, c + 1
+// on a periodic lattice of n points); computed where a gather or an atomic
+// to the grid needs them, so the axes carry only the unwrapped c.
+struct Wrap3 {
+    int i[3];
+};
+__device__ __forceinline__ Wrap3 wrap3(int c, int n) {
+    const int m = wrapi(c, n);
+    return {{m == 0 ? n - 1 : m - 1, m, m == n - 1 ? 0 : m + 1}};
+}
+
 // a[k] by selects: with k a loop counter that is not unrolled, indexing the
 // array would place it in scratch memory
 template <typename T>
@@ -205,9 +211,10 @@ __device__ __forceinline__ void mls_fit_with(const MlsAxis &X, const MlsAxis &Y,
 template <typename R, int KZ = 3>
 __device__ __forceinline__ void mls_fit(const MlsAxis &X, const MlsAxis &Y, const MlsAxis &Z,
                                         const MlsGrid &g, const R *__restrict__ q, double a[4]) {
+    const Wrap3 wx = wrap3(X.c, g.nx), wy = wrap3(Y.c, g.ny), wz = wrap3(Z.c, g.nz);
     mls_fit_with<KZ>(X, Y, Z, a, [&](int i, int j, int k) {
-        const int zk = KZ == 1 ? pick3(Z.idx, k) : Z.idx[k];
-        return (double)q[(int64_t)zk * g.plane + (int64_t)Y.idx[j] * g.nx + X.idx[i]];
+        const int zk = KZ == 1 ? pick3(wz.i, k) : wz.i[k];
+        return (double)q[(int64_t)zk * g.plane + (int64_t)wy.i[j] * g.nx + wx.i[i]];
     });
 }
 
@@ -323,8 +330,9 @@ __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X
         const double cl = area * hl / (sphi * g.h * g.h * g.h);
         const double Fd = (double)Fm[3 * f + d] * cl;
         R *fd = fld + d * g.field;
+        const Wrap3 wx = wrap3(AX.c, g.nx), wy = wrap3(AY.c, g.ny), wz = wrap3(AZ.c, g.nz);
         mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
-            unsafeAtomicAdd(fd + (int64_t)AZ.idx[k] * g.plane + (int64_t)AY.idx[j] * g.nx + AX.idx[i],
+            unsafeAtomicAdd(fd + (int64_t)wz.i[k] * g.plane + (int64_t)wy.i[j] * g.nx + wx.i[i],
                             (R)(ph * Fd));
         });
     }
@@ -359,8 +367,9 @@ __global__ __launch_bounds__(256) void k_direct_forcing_mls(
         const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
         const double Fd = Fl * area * hl / (sphi * g.h * g.h * g.h);
         R *fd = fld + d * g.field;
+        const Wrap3 wx = wrap3(AX.c, g.nx), wy = wrap3(AY.c, g.ny), wz = wrap3(AZ.c, g.nz);
         mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
-            unsafeAtomicAdd(fd + (int64_t)AZ.idx[k] * g.plane + (int64_t)AY.idx[j] * g.nx + AX.idx[i],
+            unsafeAtomicAdd(fd + (int64_t)wz.i[k] * g.plane + (int64_t)wy.i[j] * g.nx + wx.i[i],
                             (R)(ph * Fd));
         });
     }
@@ -632,7 +641,8 @@ __global__ __launch_bounds__(NT) void k_interp_mls_units(MlsUnitArgs a) {
         if (T != nullptr && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Lx && oy + 2 < Ly &&
             oz + 2 < Lz) {
             const R *base = T + (oz * (int)Ly + oy) * (int)Lx + ox;
-            mls_fit_with<3>(X, Y, Z, out, [&](int i, int j, int k) {
+            // one z plane (nine LDS reads) at a time: fewer registers
+            mls_fit_with<1>(X, Y, Z, out, [&](int i, int j, int k) {
                 return (double)base[(k * (int)Ly + j) * (int)Lx + i];
             });
         } else {
@@ -792,9 +802,11 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
                     lds_add(base + (k * Ty + j) * Tx + i, ph * Fd);
                 });
             } else {
+                const Wrap3 wx = wrap3(AX.c, g.nx), wy = wrap3(AY.c, g.ny),
+                            wz = wrap3(AZ.c, g.nz);
                 mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
-                    unsafeAtomicAdd(fd + (int64_t)AZ.idx[k] * g.plane + (int64_t)AY.idx[j] * g.nx +
-                                        AX.idx[i],
+                    unsafeAtomicAdd(fd + (int64_t)wz.i[k] * g.plane + (int64_t)wy.i[j] * g.nx +
+                                        wx.i[i],
                                     (R)(ph * Fd));
                 });
             }
