@@ -41,7 +41,8 @@ from . import native as N
 #: Stage 1: workgroup shapes (threads, workgroups per compute unit); {} is the
 #: default split (units above 1536 nodes on 768 threads, the rest on 384, two
 #: per compute unit).  128-thread units need small patches for their tiles
-#: to fit four to a compute unit, so that shape comes with its patch size.
+#: to fit four or six to a compute unit, so those shapes come with their
+#: patch size.
 STAGE1 = (
     {},
     {"threads": 768},
@@ -50,6 +51,7 @@ STAGE1 = (
     {"threads": 256, "wg_per_cu": 2},
     {"threads": 256, "wg_per_cu": 3},
     {"threads": 128, "wg_per_cu": 4, "patch_owned": 256},
+    {"threads": 128, "wg_per_cu": 6, "patch_owned": 128},
 )
 #: Stage 2: unit splits tried on the best stage-1 shape.
 STAGE2 = (

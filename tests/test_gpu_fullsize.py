@@ -122,7 +122,8 @@ def uneven():
 #: 384-thread workgroups per compute unit, most cell boxes in LDS tiles, the
 #: others spread and interpolated directly against the grid)
 UNEVEN_SHAPES = {"default": None, "t384_two_per_cu": {"threads": 384, "wg_per_cu": 2},
-                 "t128_four_per_cu": {"threads": 128, "wg_per_cu": 4, "patch_owned": 256}}
+                 "t128_four_per_cu": {"threads": 128, "wg_per_cu": 4, "patch_owned": 256},
+                 "t128_six_per_cu": {"threads": 128, "wg_per_cu": 6, "patch_owned": 128}}
 
 
 @pytest.mark.parametrize("shape", list(UNEVEN_SHAPES))

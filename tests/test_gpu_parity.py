@@ -186,6 +186,7 @@ LAUNCH_SHAPES = {
     "t256_three_per_cu": {"threads": 256, "wg_per_cu": 3},
     "t256_small_units": {"threads": 256, "wg_per_cu": 2, "unit_nodes": 384, "patch_owned": 128},
     "t128_four_per_cu": {"threads": 128, "wg_per_cu": 4, "patch_owned": 256},
+    "t128_six_per_cu": {"threads": 128, "wg_per_cu": 6, "patch_owned": 128},
 }
 
 
