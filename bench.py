@@ -463,6 +463,11 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
         raise SystemExit(f"device status {code} flags {flags} in the uneven leg")
     touched = touched_points_device(wl.X, wl.grid, device=dev)
     ub = algorithmic_bytes(wl, touched, 4)
+    # counters of the step kernel alone (the geometry and commit passes of the
+    # patched bodies excluded), when taken on these sources and this shape
+    launch = {"threads": plan.step_threads, "tile_bytes": plan.tile_bytes, "units": plan.n_units}
+    traffic, traffic_src = load_traffic(wl.name, "f32", launch)
+    valu = load_valu(wl.name, "f32", launch, graph)
     out = {"uneven_workload": wl.name, "uneven_nodes": wl.n_nodes, "uneven_options": opts,
            "uneven_autotune": [{"options": r["options"], "ms": r["ms"], "stage": r["stage"]}
                                for r in tuned],
@@ -473,7 +478,10 @@ def uneven_leg(N, W, dev, torch, log, steps=10, sample=256):
            "uneven_roofline": roofline_block(
                ub, graph, "k_step_fused<float, %d, false> + geometry and commit passes"
                % plan.step_threads, {"touched_grid_points": touched,
-                                     "bytes_per_node": ub / wl.n_nodes})}
+                                     "bytes_per_node": ub / wl.n_nodes,
+                                     "traffic": traffic, "traffic_source": traffic_src,
+                                     "traffic_kernel": "k_step_fused only",
+                                     "valu_issue": valu})}
     log(f"uneven: {ub / 1e9:.3f} GB algorithmic per step, "
         f"{out['uneven_roofline']['frac']:.1%} of HBM at the graph replay's time")
     del gr, plan
