@@ -47,6 +47,12 @@ CASES = {
     # per-marker kernels with device atomics
     "unfused_sheet_drop": sheet_and_drop,
     "wrapped_drops": wrapped_drops,
+    # the staged velocity of the interpolation fits one lattice at a time
+    # (a box of about 21^3 points beside 2562 positions)
+    "drop_L4_box_one_lattice": lambda: W.small_suspension(1, 4, 128, r=0.0625),
+    # a box larger than any tile: interpolation gathers from u, spreading
+    # adds to f directly
+    "drop_L4_box_too_big": lambda: W.small_suspension(1, 4, 128, r=0.3),
 }
 
 
