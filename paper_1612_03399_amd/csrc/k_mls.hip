@@ -750,24 +750,61 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
     // tile points lo - 1 .. hi + 2 per axis
     const long long Lx = (long long)hi[0] - lo[0] + 4, Ly = (long long)hi[1] - lo[1] + 4,
                     Lz = (long long)hi[2] - lo[2] + 4;
-    const bool use_tile = Lx <= g.nx && Ly <= g.ny && Lz <= g.nz && Lx * Ly * Lz * 8 <= a.tile_bytes;
-    const int Tx = use_tile ? (int)Lx : 1, Ty = use_tile ? (int)Ly : 1, Tz = use_tile ? (int)Lz : 1;
-    TileGeom tg{{lo[0], lo[1], lo[2]}, 1, 1, 1, 0, g.nx, g.ny, g.nz, g.plane,
-                {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    if (use_tile) tg = mls_tile_geom<NT>(lo, Tx, Ty, Tz, g);
+    const bool box_ok = Lx <= g.nx && Ly <= g.ny && Lz <= g.nz;
+    const long long Tl = Lx * Ly * Lz;
+    // all three lattices' tiles at once when they fit (each face then
+    // computes its geometry and half-cell axes once), else one per pass.
+    // Direct forcing keeps one lattice per pass: with its fits beside the
+    // shared axes it spills (56 registers against 12).
+    const bool all3 = !DF && box_ok && 3 * Tl * 8 <= a.tile_bytes;
+    const bool use_tile = box_ok && Tl * 8 <= a.tile_bytes;
+    const int Tx = (int)Lx, Ty = (int)Ly, Tz = (int)Lz;
     bool bad = false;
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-        R *fd = fld + d * g.field;
-        if (use_tile) {
-            for (int t = tid; t < tg.T; t += NT) tile[t] = 0.0;
-            lds_barrier();
+    // face pf (area, the axes of lattice d) into T, the lattice's tile, or,
+    // without a tile or outside it, into f directly
+    const auto spread_one = [&](int d, const MlsAxis &AX, const MlsAxis &AY, const MlsAxis &AZ,
+                                double area, int64_t pf, double *T) {
+        bad |= !(AX.ok && AY.ok && AZ.ok);
+        const double sphi = mls_phi_sum(AX, AY, AZ);
+        const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
+        const double cl = area * hl / (sphi * g.h * g.h * g.h);
+        double Fl;
+        if constexpr (DF) {
+            double fit[4];
+            mls_fit<R>(AX, AY, AZ, g, (const R *)a.u + d * g.field, fit);
+            Fl = ((double)((const R *)a.Vb)[3 * pf + d] - fit[0]) * a.inv_dt;
+            if (a.Fout != nullptr) ((R *)a.Fout)[3 * pf + d] = (R)Fl;
+        } else {
+            Fl = (double)Fm[3 * pf + d];
         }
+        const double Fd = Fl * cl;
+        // support point c - 1 + j is tile point c + j - lo (inside the tile
+        // for every marker the box was taken from; checked all the same)
+        const int ox = AX.c - lo[0], oy = AY.c - lo[1], oz = AZ.c - lo[2];
+        if (T != nullptr && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Tx && oy + 2 < Ty &&
+            oz + 2 < Tz) {
+            double *base = T + (oz * Ty + oy) * Tx + ox;
+            mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
+                lds_add(base + (k * Ty + j) * Tx + i, ph * Fd);
+            });
+        } else {
+            R *fd = fld + d * g.field;
+            const Wrap3 wx = wrap3(AX.c, g.nx), wy = wrap3(AY.c, g.ny), wz = wrap3(AZ.c, g.nz);
+            mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
+                unsafeAtomicAdd(fd + (int64_t)wz.i[k] * g.plane + (int64_t)wy.i[j] * g.nx + wx.i[i],
+                                (R)(ph * Fd));
+            });
+        }
+    };
+    // record order also for whole units: the records of a run of 64 touch
+    // distinct nodes, so the lanes of a wave add into distinct tile points
+    // (in face order neighbouring faces of the subdivided mesh collide: 1.30
+    // against 0.72 ms on the 1000-drop batch)
+    if (all3) {
+        const TileGeom tg = mls_tile_geom<NT>(lo, Tx, Ty, Tz, g);
+        for (int t = tid; t < 3 * tg.T; t += NT) tile[t] = 0.0;
+        lds_barrier();
         for (int t = tid; t < F; t += NT) {
-            // record order also for whole units: the records of a run of 64
-            // touch distinct nodes, so the lanes of a wave add into distinct
-            // tile points (in face order neighbouring faces of the subdivided
-            // mesh collide: 1.30 against 0.72 ms on the 1000-drop batch)
             int q[3];
             const int64_t pf = unit_face(a, false, 0, n0, f0, N, t, q);
             if (pf < 0) continue;
@@ -775,49 +812,57 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
             const vec3<double> n = cross(xb - xa, xc - xa);
             const double area = 0.5 * sqrt(dot(n, n));
             const vec3<double> p = marker_at(xs, q);
-            MlsAxis AX, AY, AZ;
-            mls_axes(p, d, g, AX, AY, AZ);
-            bad |= !(AX.ok && AY.ok && AZ.ok);
-            const double sphi = mls_phi_sum(AX, AY, AZ);
-            const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
-            const double cl = area * hl / (sphi * g.h * g.h * g.h);
-            double Fl;
-            if constexpr (DF) {
-                double fit[4];
-                mls_fit<R>(AX, AY, AZ, g, (const R *)a.u + d * g.field, fit);
-                Fl = ((double)((const R *)a.Vb)[3 * pf + d] - fit[0]) * a.inv_dt;
-                if (a.Fout != nullptr) ((R *)a.Fout)[3 * pf + d] = (R)Fl;
-            } else {
-                Fl = (double)Fm[3 * pf + d];
-            }
-            const double Fd = Fl * cl;
-            // support point c - 1 + j is tile point c + j - lo (inside the tile
-            // for every marker the box was taken from; checked all the same)
-            const int ox = AX.c - lo[0], oy = AY.c - lo[1], oz = AZ.c - lo[2];
-            const bool in_tile = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Tx &&
-                                 oy + 2 < Ty && oz + 2 < Tz;
-            if (in_tile) {
-                double *base = tile + (oz * Ty + oy) * Tx + ox;
-                mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
-                    lds_add(base + (k * Ty + j) * Tx + i, ph * Fd);
-                });
-            } else {
-                const Wrap3 wx = wrap3(AX.c, g.nx), wy = wrap3(AY.c, g.ny),
-                            wz = wrap3(AZ.c, g.nz);
-                mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
-                    unsafeAtomicAdd(fd + (int64_t)wz.i[k] * g.plane + (int64_t)wy.i[j] * g.nx +
-                                        wx.i[i],
-                                    (R)(ph * Fd));
-                });
+            MlsHalf H;
+            mls_half_axes(p, g, H);
+            // one lattice at a time (unrolled, the three interleave and spill)
+#pragma unroll 1
+            for (int d = 0; d < 3; ++d) {
+                MlsAxis I;
+                mls_int_axis(p, d, g, I);
+                spread_one(d, axis_x(H, I, d), axis_y(H, I, d), axis_z(H, I, d), area, pf,
+                           tile + d * tg.T);
             }
         }
-        if (use_tile) {
-            lds_barrier();
-            for (TileCursor c = TileCursor::first(tg); c.t < tg.T; c.template next<NT>(tg)) {
-                const double v = tile[c.t];
-                if (v != 0.0) unsafeAtomicAdd(fd + c.grid_index(tg), (R)v);
+        lds_barrier();
+        for (TileCursor c = TileCursor::first(tg); c.t < tg.T; c.template next<NT>(tg)) {
+            const int64_t gi = c.grid_index(tg);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double v = tile[d * tg.T + c.t];
+                if (v != 0.0) unsafeAtomicAdd(fld + d * g.field + gi, (R)v);
             }
-            lds_barrier();
+        }
+    } else {
+        TileGeom tg{{lo[0], lo[1], lo[2]}, 1, 1, 1, 0, g.nx, g.ny, g.nz, g.plane,
+                    {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        if (use_tile) tg = mls_tile_geom<NT>(lo, Tx, Ty, Tz, g);
+#pragma unroll 1
+        for (int d = 0; d < 3; ++d) {
+            if (use_tile) {
+                for (int t = tid; t < tg.T; t += NT) tile[t] = 0.0;
+                lds_barrier();
+            }
+            for (int t = tid; t < F; t += NT) {
+                int q[3];
+                const int64_t pf = unit_face(a, false, 0, n0, f0, N, t, q);
+                if (pf < 0) continue;
+                const vec3<double> xa = ldx(xs, q[0]), xb = ldx(xs, q[1]), xc = ldx(xs, q[2]);
+                const vec3<double> n = cross(xb - xa, xc - xa);
+                const double area = 0.5 * sqrt(dot(n, n));
+                const vec3<double> p = marker_at(xs, q);
+                MlsAxis AX, AY, AZ;
+                mls_axes(p, d, g, AX, AY, AZ);
+                spread_one(d, AX, AY, AZ, area, pf, use_tile ? tile : nullptr);
+            }
+            if (use_tile) {
+                lds_barrier();
+                R *fd = fld + d * g.field;
+                for (TileCursor c = TileCursor::first(tg); c.t < tg.T; c.template next<NT>(tg)) {
+                    const double v = tile[c.t];
+                    if (v != 0.0) unsafeAtomicAdd(fd + c.grid_index(tg), (R)v);
+                }
+                lds_barrier();
+            }
         }
     }
     if (bad) atomicOr(a.status, IP_STATUS_NONFINITE);
