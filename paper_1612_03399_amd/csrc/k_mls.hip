@@ -762,16 +762,27 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
     bool bad = false;
     // face pf (area, the axes of lattice d) into T, the lattice's tile, or,
     // without a tile or outside it, into f directly
+    // UT: lattice d's velocity staged over the box (direct forcing), or null
     const auto spread_one = [&](int d, const MlsAxis &AX, const MlsAxis &AY, const MlsAxis &AZ,
-                                double area, int64_t pf, double *T) {
+                                double area, int64_t pf, double *T, const R *UT) {
         bad |= !(AX.ok && AY.ok && AZ.ok);
         const double sphi = mls_phi_sum(AX, AY, AZ);
         const double hl = (1.0 / 3.0) * sphi * (3.0 * g.h);
         const double cl = area * hl / (sphi * g.h * g.h * g.h);
+        const int ox = AX.c - lo[0], oy = AY.c - lo[1], oz = AZ.c - lo[2];
+        const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Tx && oy + 2 < Ty &&
+                            oz + 2 < Tz;
         double Fl;
         if constexpr (DF) {
             double fit[4];
-            mls_fit<R>(AX, AY, AZ, g, (const R *)a.u + d * g.field, fit);
+            if (UT != nullptr && inside) {
+                const R *base = UT + (oz * Ty + oy) * Tx + ox;
+                mls_fit_with<1>(AX, AY, AZ, fit, [&](int i, int j, int k) {
+                    return (double)base[(k * Ty + j) * Tx + i];
+                });
+            } else {
+                mls_fit<R>(AX, AY, AZ, g, (const R *)a.u + d * g.field, fit);
+            }
             Fl = ((double)((const R *)a.Vb)[3 * pf + d] - fit[0]) * a.inv_dt;
             if (a.Fout != nullptr) ((R *)a.Fout)[3 * pf + d] = (R)Fl;
         } else {
@@ -780,9 +791,7 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
         const double Fd = Fl * cl;
         // support point c - 1 + j is tile point c + j - lo (inside the tile
         // for every marker the box was taken from; checked all the same)
-        const int ox = AX.c - lo[0], oy = AY.c - lo[1], oz = AZ.c - lo[2];
-        if (T != nullptr && ox >= 0 && oy >= 0 && oz >= 0 && ox + 2 < Tx && oy + 2 < Ty &&
-            oz + 2 < Tz) {
+        if (T != nullptr && inside) {
             double *base = T + (oz * Ty + oy) * Tx + ox;
             mls_for_each_phi(AX, AY, AZ, [&](int i, int j, int k, double ph) {
                 lds_add(base + (k * Ty + j) * Tx + i, ph * Fd);
@@ -820,7 +829,7 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
                 MlsAxis I;
                 mls_int_axis(p, d, g, I);
                 spread_one(d, axis_x(H, I, d), axis_y(H, I, d), axis_z(H, I, d), area, pf,
-                           tile + d * tg.T);
+                           tile + d * tg.T, nullptr);
             }
         }
         lds_barrier();
@@ -836,10 +845,16 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
         TileGeom tg{{lo[0], lo[1], lo[2]}, 1, 1, 1, 0, g.nx, g.ny, g.nz, g.plane,
                     {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         if (use_tile) tg = mls_tile_geom<NT>(lo, Tx, Ty, Tz, g);
+        // direct forcing: lattice d's velocity staged beside its force tile
+        // when both fit, so the fits read LDS instead of gathering from u
+        R *utile = DF && use_tile && Tl * (8 + (long long)sizeof(R)) <= a.tile_bytes
+                       ? (R *)(tile + Tl)
+                       : nullptr;
 #pragma unroll 1
         for (int d = 0; d < 3; ++d) {
             if (use_tile) {
                 for (int t = tid; t < tg.T; t += NT) tile[t] = 0.0;
+                if (utile != nullptr) stage_tile<NT, R>(utile, (const R *)a.u + d * g.field, tg);
                 lds_barrier();
             }
             for (int t = tid; t < F; t += NT) {
@@ -852,7 +867,7 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
                 const vec3<double> p = marker_at(xs, q);
                 MlsAxis AX, AY, AZ;
                 mls_axes(p, d, g, AX, AY, AZ);
-                spread_one(d, AX, AY, AZ, area, pf, use_tile ? tile : nullptr);
+                spread_one(d, AX, AY, AZ, area, pf, use_tile ? tile : nullptr, utile);
             }
             if (use_tile) {
                 lds_barrier();
