@@ -622,7 +622,16 @@ __global__ __launch_bounds__(NT) void k_interp_mls_units(MlsUnitArgs a) {
 
     int lo[3], hi[3];
     load_positions<NT>(xs, a.X, whole, n0, gid, NL, N, g.inv_h, lo, hi);
-    owned_marker_box<NT>(xs, frec, F, N, g.inv_h, lo, hi, ired, red);
+    if (whole) {
+        // a centroid lies between its corners, so its cell lies in the box of
+        // the body's node cells (the same monotone cell function; a marker a
+        // rounding pushes outside is caught by the in-tile check): no pass
+        // over the face records is needed to find the box
+        double none[1] = {0.0};
+        block_box_sums<NT, 1>(lo, hi, none, ired, red);
+    } else {
+        owned_marker_box<NT>(xs, frec, F, N, g.inv_h, lo, hi, ired, red);
+    }
     if (lo[0] > hi[0]) return;                     // no owned marker (uniform)
     const long long Lx = (long long)hi[0] - lo[0] + 4, Ly = (long long)hi[1] - lo[1] + 4,
                     Lz = (long long)hi[2] - lo[2] + 4;
