@@ -383,19 +383,9 @@ __global__ __launch_bounds__(256) void k_direct_forcing_mls(
 // tau = mu (G + G^T); the load is sum_s s (-p n + tau n) A.
 template <typename R>
 __device__ __forceinline__ void probe_face(
-    int64_t f, const double *__restrict__ X, const int32_t *__restrict__ faces,
-    const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B,
-    const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, const MlsGrid &g,
-    double mu, double out[3], uint32_t *status) {
-    // body of face f: the last b with face_off[b] <= f
-    int lo = 0, hi = B - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (face_off[mid] <= f)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
+    int64_t f, int lo, const double *__restrict__ X, const int32_t *__restrict__ faces,
+    const uint8_t *__restrict__ closed, const R *__restrict__ u, const R *__restrict__ pr,
+    const R *__restrict__ acc, const MlsGrid &g, double mu, double out[3], uint32_t *status) {
     const vec3<double> xa = ldX(X, faces[3 * f]), xb = ldX(X, faces[3 * f + 1]),
                        xc3 = ldX(X, faces[3 * f + 2]);
     const vec3<double> nn = cross(xb - xa, xc3 - xa);
@@ -476,8 +466,24 @@ __global__ __launch_bounds__(256, 2) void k_probe_loads(
     const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
     double mu, R *__restrict__ Fext, uint32_t *status) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // body of face f, the last b with face_off[b] <= f: one binary search for
+    // the wave's first face on scalar registers (the wave's faces are
+    // consecutive), then each lane steps over the few body ends before its face
+    const int64_t fl = f - (threadIdx.x & 63);
+    const int64_t fw = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(fl >> 32))
+                                  << 32) |
+                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)fl));
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (face_off[mid] <= fw)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    while (lo + 1 < B && face_off[lo + 1] <= f) ++lo;
     double v[3] = {0.0, 0.0, 0.0};
-    if (f < F) probe_face<R>(f, X, faces, face_off, closed, B, u, pr, acc, g, mu, v, status);
+    if (f < F) probe_face<R>(f, lo, X, faces, closed, u, pr, acc, g, mu, v, status);
     store3_rows(Fext, f - (threadIdx.x & 63), F, v);
 }
 
