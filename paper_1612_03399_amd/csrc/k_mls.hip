@@ -28,15 +28,22 @@
 // weights of an axis take one exponential (scaled by exp(2 d_c q^2) / w_c they
 // are exp(-q^2) exp(2 d_c q^2)^2, exp(2 d_c q^2), exp(-q^2)).
 //
-// Interpolation runs one thread per marker (its gathers of u hit in L2: the
-// faces of a body are consecutive).  Spreading on plans with work units runs
-// one workgroup per unit: the unit's positions go to LDS, each face whose
-// first corner the unit owns adds its 27 weighted values per lattice into an
-// FP64 LDS tile over the cell box of the unit's markers (ds_add_f64), and the
-// tile's non-zero points are added to f once.  A unit whose tile does not fit
-// adds into f directly.  (Measured on 1000 level-4 drops: per-marker global
-// atomics 18.5 ms, the tiled form 0.8 ms; a tiled interpolation was slower
-// than the per-marker one, 0.69 against 0.61 ms.)
+// On plans with work units every transfer but the probes runs one workgroup
+// per unit, with the unit's positions in LDS:
+// * interpolation stages the three velocity lattices over the cell box of
+//   the unit's markers in LDS (or one lattice per pass when three do not
+//   fit) and fits each marker from there; a whole body takes its faces in
+//   face order, so each wave writes its rows of U whole;
+// * spreading adds each owned face's 27 weighted values per lattice into
+//   FP64 LDS tiles over the box (ds_add_f64; the three lattices in one pass
+//   when their tiles fit) and adds the tiles' non-zero points to f once;
+// * direct forcing fits the marker velocity from the lattice's velocity
+//   staged beside its force tile, then spreads as above.
+// A marker whose support leaves the box, or a unit whose box does not fit,
+// gathers from u and adds to f directly.  Plans without work units run one
+// thread per marker with device atomics.  (Measured on 1000 level-4 drops:
+// per-marker global atomics 18.5 ms for spreading, the tiled form 0.65 ms;
+// per-marker interpolation 0.38 ms, from the staged tile 0.31 ms.)
 #include <algorithm>
 #include <cmath>
 
