@@ -24,8 +24,9 @@
 //
 // The per-axis parts are shared: along any axis the three MAC lattices sit at
 // only two offsets (integer or half cells), so a marker computes six axes for
-// all three lattices (the probe kernel excepted, see there), and the three
-// weights of an axis take one exponential (scaled by exp(2 d_c q^2) / w_c they
+// all three lattices (a probe end six for its four fits, the cell-centred
+// pressure lattice taking the half-cell ones), and the three weights of an
+// axis take one exponential (scaled by exp(2 d_c q^2) / w_c they
 // are exp(-q^2) exp(2 d_c q^2)^2, exp(2 d_c q^2), exp(-q^2)).
 //
 // On plans with work units every transfer but the probes runs one workgroup
@@ -418,33 +419,26 @@ __device__ __forceinline__ void probe_face(
         const double sg = side == 0 ? 1.0 : -1.0;
         const vec3<double> y{xc.x + sg * g.h * nu.x, xc.y + sg * g.h * nu.y, xc.z + sg * g.h * nu.z};
         // the pressure lattice (cell centres) takes the half-cell axes on
-        // all three axes; velocity lattice i the integer one along axis i
-        // each fit computes its own axes: their exponentials overlap that
-        // fit's 27 gathers (sharing the half-cell axes across the four fits
-        // leaves the gathers exposed and measured slower)
+        // all three axes, velocity lattice i the integer one along axis i and
+        // the same half-cell axes along the others: six axes for the four
+        // fits.  (G + G^T) n is accumulated row by row as the fits give the
+        // rows G_i. of the velocity gradient: component i takes (G n)_i,
+        // every component j takes G_ij n_i; the loop over i is unrolled so
+        // that each lattice's axes are chosen at compile time (a choice made
+        // at run time would place the axes in scratch memory)
         double ap[4];
-        {
-            MlsAxis X, Y, Z;
-            mls_axis(y.x, 0.5, g.nx, g, X);
-            mls_axis(y.y, 0.5, g.ny, g, Y);
-            mls_axis(y.z, 0.5, g.nz, g, Z);
-            bad |= !(X.ok && Y.ok && Z.ok);
-            mls_fit<R, 1>(X, Y, Z, g, pr, ap);
-        }
-        // (G + G^T) n, accumulated row by row as the fits give the rows
-        // G_i. of the velocity gradient: component i takes (G n)_i, every
-        // component j takes G_ij n_i (no array indexed by i, which would
-        // live in scratch memory)
+        MlsHalf H;
+        mls_half_axes(y, g, H);
+        bad |= !(H.h[0].ok && H.h[1].ok && H.h[2].ok);
+        mls_fit<R, 1>(H.h[0], H.h[1], H.h[2], g, pr, ap);
         double tn0 = 0.0, tn1 = 0.0, tn2 = 0.0;
-#pragma unroll 1
+#pragma unroll
         for (int i = 0; i < 3; ++i) {
             double ai[4];
-            MlsAxis X, Y, Z;
-            mls_axis(y.x, mac_off(i, 0), g.nx, g, X);
-            mls_axis(y.y, mac_off(i, 1), g.ny, g, Y);
-            mls_axis(y.z, mac_off(i, 2), g.nz, g, Z);
-            bad |= !(X.ok && Y.ok && Z.ok);
-            mls_fit<R, 1>(X, Y, Z, g, u + i * g.field, ai);
+            MlsAxis I;
+            mls_int_axis(y, i, g, I);
+            bad |= !I.ok;
+            mls_fit<R, 1>(axis_x(H, I, i), axis_y(H, I, i), axis_z(H, I, i), g, u + i * g.field, ai);
             const double gx = ai[1] * g.inv_h, gy = ai[2] * g.inv_h, gz = ai[3] * g.inv_h;
             const double ni = i == 0 ? nu.x : (i == 1 ? nu.y : nu.z);
             const double gn = gx * nu.x + gy * nu.y + gz * nu.z;
@@ -466,13 +460,25 @@ __device__ __forceinline__ void probe_face(
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup i to XCD i mod 8),
+// each XCD with its own L2.  This numbering gives XCD x one contiguous range
+// of the n logical blocks (its k-th workgroup takes block start_x + k), so
+// the consecutive faces of a body, whose probe ends read the same grid
+// points, are fetched into one L2 rather than into all eight.  A bijection
+// of 0 .. n - 1 whatever the hardware's order.
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t n = gridDim.x, i = blockIdx.x;
+    const int64_t q = n / 8, r = n % 8, x = i % 8, k = i / 8;
+    return x * q + (x < r ? x : r) + k;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256, 2) void k_probe_loads(
     const double *__restrict__ X, const int32_t *__restrict__ faces,
     const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
     const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
     double mu, R *__restrict__ Fext, uint32_t *status) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     // body of face f, the last b with face_off[b] <= f: one binary search for
     // the wave's first face on scalar registers (the wave's faces are
     // consecutive), then each lane steps over the few body ends before its face
@@ -602,6 +608,38 @@ __device__ __forceinline__ TileGeom mls_tile_geom(const int lo[3], int Tx, int T
     return tg;
 }
 
+// The three lattices' tiles in one walk: three loads per tile point, U points
+// per thread in flight.
+template <int NT, typename R, int U = 8>
+__device__ __forceinline__ void stage_tiles3(R *__restrict__ tile, const R *__restrict__ field,
+                                             int64_t fstride, int Tl, const TileGeom &g) {
+    TileCursor c = TileCursor::first(g);
+    while (c.t < g.T) {
+        R v0[U], v1[U], v2[U];
+        int t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            t[k] = c.t;
+            if (c.t < g.T) {
+                const int64_t i = c.grid_index(g);
+                v0[k] = field[i];
+                v1[k] = field[fstride + i];
+                v2[k] = field[2 * fstride + i];
+            } else {
+                v0[k] = v1[k] = v2[k] = (R)0;
+            }
+            c.template next<NT>(g);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (t[k] < g.T) {
+                tile[t[k]] = v0[k];
+                tile[Tl + t[k]] = v1[k];
+                tile[2 * Tl + t[k]] = v2[k];
+            }
+    }
+}
+
 // Interpolation at the faces owned by one work unit (one workgroup per unit).
 // The velocity over the cell box of the unit's markers is staged in LDS,
 // coalesced, so each marker's 81 reads come from LDS instead of scattered
@@ -681,7 +719,7 @@ __global__ __launch_bounds__(NT) void k_interp_mls_units(MlsUnitArgs a) {
         // all three lattices per marker, from the tile (per_pass 3) or from u
         if (per_pass == 3) {
             const TileGeom tg = mls_tile_geom<NT>(lo, (int)Lx, (int)Ly, (int)Lz, g);
-            for (int l = 0; l < 3; ++l) stage_tile<NT, R>(tile + l * Tl, u + l * g.field, tg);
+            stage_tiles3<NT, R>(tile, u, g.field, (int)Tl, tg);
             lds_barrier();
         }
         for (int t0 = tid - lane; t0 < F; t0 += NT) {          // wave-uniform bound
