@@ -472,7 +472,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 3 : 1) void k_step_vjp_fused(VjpArg
     __shared__ int cnt_bins[kCountBins + 1];
 
     const int tid = threadIdx.x;
-    const int w = a.unit_base + (int)blockIdx.x;
+    const int w = a.unit_base + xcd_unit((int)blockIdx.x, (int)gridDim.x);
     const int b = a.wu_body[w];
     const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
     const bool whole = nl1 == nl0;

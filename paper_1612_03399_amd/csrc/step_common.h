@@ -33,6 +33,19 @@ __device__ __forceinline__ double uniform(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Unit of workgroup i among n.  Workgroup i runs on XCD i mod 8, each XCD
+// with its own L2.  The units are dealt to the XCDs in chunks of 16
+// consecutive ones, so that neighbouring units (the patches of one body,
+// which share grid lines) share an L2, while every XCD still takes units of
+// every size class; the last partial round of 128 units keeps the plain
+// order.  A bijection of 0 .. n - 1.
+__device__ __forceinline__ int xcd_unit(int i, int n) {
+    constexpr int C = 16, G = 8 * C;
+    if (i >= n / G * G) return i;
+    const int x = i % 8, k = i / 8;
+    return (k / C) * G + x * C + (k % C);
+}
+
 // Workgroup barrier that orders LDS accesses only: outstanding global memory
 // operations (the grid atomics of a tile flush, prefetch loads) stay in
 // flight across it.

@@ -329,6 +329,8 @@ bool build_work_units(const ip_mesh *m, int whole_max, int nmax_unit, int fmax_u
     // largest units first (the tail of the launch runs the small ones), in
     // size classes of 64 nodes; within a class the patches of a body stay
     // together, so that units running side by side share their grid lines
+    // (the unit kernels deal consecutive units to one XCD in chunks, so
+    // that such neighbours also share an L2)
     std::vector<int32_t> idx(out.units.size());
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
