@@ -32,16 +32,18 @@ KERNEL_SOURCES = ["paper_1612_03399_amd/csrc/k_step.hip", "paper_1612_03399_amd/
                   "paper_1612_03399_amd/csrc/elements.h",
                   "paper_1612_03399_amd/csrc/ipibm_internal.h",
                   "paper_1612_03399_amd/csrc/workunits.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_fused_{workload}_{dtype}.json")
+# the reverse step's counters depend on its own kernel too
+REVERSE_SOURCES = KERNEL_SOURCES + ["paper_1612_03399_amd/csrc/k_backward.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_{workload}_{dtype}.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_k_step_fused_{workload}_{dtype}.json")
 # VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
 # SIMD every 4 cycles (16 lanes per cycle)
 VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=KERNEL_SOURCES):
     h = hashlib.sha1()
-    for p in KERNEL_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -132,15 +134,15 @@ def algorithmic_bytes(wl, touched, real_bytes):
     return nodes + edges + faces + bodies + grid
 
 
-def load_traffic(workload, dtype, launch):
+def load_traffic(workload, dtype, launch, kernel="k_step_fused", sources=KERNEL_SOURCES):
     """Measured HBM bytes per launch from the committed counter summary, when it
     was taken on the current kernel sources and launch shape (else None)."""
-    path = TRAFFIC_FILE.format(workload=workload, dtype=dtype)
+    path = TRAFFIC_FILE.format(kernel=kernel, workload=workload, dtype=dtype)
     if not os.path.exists(path):
         return None, None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash(sources):
         return None, "stale (kernel changed since the counters were taken)"
     if t.get("launch") != launch:
         return None, f"taken with launch shape {t.get('launch')}, not {launch}"
@@ -395,12 +397,20 @@ def backward_leg(N, W, bodies, dev, torch, log, steps=10, reps=3):
     rb = reverse_bytes(wl, touched)
     log(f"reverse step kernel: {t_rev:.4f} ms against {t_fwd:.4f} ms forward "
         f"({t_rev / t_fwd:.2f}x), {rb / (t_rev * 1e-3) / (HBM_PEAK_GBS * 1e9):.1%} of HBM")
+    launch = {"threads": plan.step_threads, "tile_bytes": plan.tile_bytes, "units": plan.n_units}
+    rr = roofline_block(rb, t_rev, f"k_step_vjp_fused<{plan.step_threads}, false>",
+                        {"touched_grid_points": touched, "launch": launch})
+    traffic, traffic_src = load_traffic(wl.name, "f64", launch, kernel="k_step_vjp_fused",
+                                        sources=REVERSE_SOURCES)
+    if traffic is not None:
+        rr.update({"traffic": traffic, "traffic_source": traffic_src})
+    elif traffic_src is not None:
+        rr["traffic_note"] = traffic_src
     out = {"diff_workload": wl.name, "diff_steps": steps, "diff_fwd_ms": f, "diff_bwd_ms": b,
            "diff_bwd_over_fwd": b / f, "diff_loss": float(loss.item()),
            "reverse_step_ms": t_rev, "forward_step_ms": t_fwd,
            "reverse_over_forward_step": t_rev / t_fwd,
-           "reverse_roofline": roofline_block(rb, t_rev, "k_step_vjp_fused<768, false>",
-                                              {"touched_grid_points": touched})}
+           "reverse_roofline": rr}
     del plan, X, Xf, lam, lam2, gk, gu, f_grid, u
     torch.cuda.empty_cache()
     return out
