@@ -775,6 +775,15 @@ def main():
         extras[f"{other}_roofline"] = roofline_block(
             b2, ms2, f"k_step_fused<{'double' if other == 'f64' else 'float'}, "
                      f"{plan2.step_threads}, false>", {"bytes_per_node": b2 / wl.n_nodes})
+        launch2 = {"threads": plan2.step_threads, "tile_bytes": plan2.tile_bytes,
+                   "units": plan2.n_units}
+        traffic2, traffic2_src = load_traffic(wl.name, other, launch2)
+        if traffic2 is not None:
+            extras[f"{other}_roofline"].update({"traffic": traffic2,
+                                                "traffic_source": traffic2_src})
+        valu2 = load_valu(wl.name, other, launch2, ms2)
+        if valu2 is not None:
+            extras[f"{other}_roofline"]["valu_issue"] = valu2
         log(f"{other}: graph replay {ms2:.4f} ms/step, eager {ms2e:.4f} ms/step, "
             f"{extras[f'{other}_roofline']['frac']:.1%} of HBM")
         del plan2, X2, u2, f2
