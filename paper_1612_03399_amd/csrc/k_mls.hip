@@ -653,7 +653,7 @@ __global__ __launch_bounds__(NT) void k_interp_mls_units(MlsUnitArgs a) {
     __shared__ double red[NT / 64];
     __shared__ int ired[6 * (NT / 64)];
     const int tid = threadIdx.x;
-    const int w = blockIdx.x;
+    const int w = xcd_unit((int)blockIdx.x, (int)gridDim.x);
     const int b = a.wu_body[w];
     const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
     const bool whole = nl1 == nl0;
@@ -786,7 +786,7 @@ __global__ __launch_bounds__(NT) void k_spread_mls_units(MlsUnitArgs a) {
     __shared__ double red[NT / 64];
     __shared__ int ired[6 * (NT / 64)];
     const int tid = threadIdx.x;
-    const int w = blockIdx.x;
+    const int w = xcd_unit((int)blockIdx.x, (int)gridDim.x);
     const int b = a.wu_body[w];
     const int64_t nl0 = a.wu_noff[2 * w], nl1 = a.wu_noff[2 * w + 1];
     const bool whole = nl1 == nl0;
