@@ -36,6 +36,9 @@ CASES = {
     # a shell split into patches by the fused reverse step
     "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
                                            cells_per_unit=96),
+    # 300 units: two full rounds of the chunked deal of units to the XCDs
+    # (128 units each) and a ragged tail of 44 in plain order
+    "many_L1_64": lambda: W.small_suspension(300, 1, 64, r=0.03),
 }
 
 

@@ -53,6 +53,9 @@ CASES = {
     # a box larger than any tile: interpolation gathers from u, spreading
     # adds to f directly
     "drop_L4_box_too_big": lambda: W.small_suspension(1, 4, 128, r=0.3),
+    # 300 units: two full rounds of the chunked deal of units to the XCDs
+    # (128 units each) and a ragged tail of 44 in plain order
+    "many_L1_64": lambda: W.small_suspension(300, 1, 64, r=0.03),
 }
 
 

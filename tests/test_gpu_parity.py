@@ -45,6 +45,9 @@ CASES = {
     # a 16 002-node shell: the fused step splits it into patches with halos
     "ventricle_patched": lambda: W.config3(freq=40, leaflet_quads=30, noise_rel=0.2,
                                            cells_per_unit=96),
+    # 300 units: two full rounds of the chunked deal of units to the XCDs
+    # (128 units each) and a ragged tail of 44 in plain order
+    "many_L1_64": lambda: W.small_suspension(300, 1, 64, r=0.03),
 }
 
 
@@ -191,7 +194,8 @@ LAUNCH_SHAPES = {
 
 
 @pytest.mark.parametrize("shape", list(LAUNCH_SHAPES))
-@pytest.mark.parametrize("case", ["four_L4_128", "uneven_small", "ventricle_patched"])
+@pytest.mark.parametrize("case", ["four_L4_128", "uneven_small", "ventricle_patched",
+                                  "many_L1_64"])
 def test_step_parity_launch_shapes(case, shape):
     say("step shape", case, shape)
     opts = LAUNCH_SHAPES[shape]
