@@ -7,6 +7,7 @@
 
 #include "elements.h"
 #include "ipibm_internal.h"
+#include "xcd.h"
 
 namespace {
 
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_geometry(
 template <typename R>
 __global__ void k_reference_edges(const double *__restrict__ X, const int4 *__restrict__ e4,
                                   int64_t E, R *__restrict__ l0, R *__restrict__ cs0) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int4 q = e4[e];
     const vec3<double> x1 = ldX(X, q.x), x2 = ldX(X, q.y);
@@ -77,7 +78,7 @@ __global__ void k_reference_edges(const double *__restrict__ X, const int4 *__re
 template <typename R>
 __global__ void k_reference_faces(const double *__restrict__ X, const int32_t *__restrict__ faces,
                                   int64_t F, R *__restrict__ A0) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const int32_t *t = faces + 3 * f;
     const vec3<double> xi = ldX(X, t[0]);
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kElemThreads) void k_edges(
     const int64_t *__restrict__ edge_off, int B, int64_t E, const R *__restrict__ l0,
     const R *__restrict__ cs0, const double *__restrict__ ks, const double *__restrict__ kb,
     const double *__restrict__ ew, R *__restrict__ slots, uint32_t *__restrict__ status) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int b = body_of(edge_off, B, e);
     const double kse = ew ? ks[b] * ew[2 * e] : ks[b];
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(kElemThreads) void k_faces(
     const double *__restrict__ V0, const double *__restrict__ Vcur,
     const uint8_t *__restrict__ closed, const double *__restrict__ kA,
     const double *__restrict__ kV, R *__restrict__ slots, uint32_t *__restrict__ status) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const int b = body_of(face_off, B, f);
     const int32_t *t = faces + 3 * f;
@@ -152,7 +153,7 @@ template <typename R>
 __global__ void k_gather(const int32_t *__restrict__ ptr, const int32_t *__restrict__ slot_ids,
                          const R *__restrict__ slots, int64_t N, R *__restrict__ F,
                          uint32_t *__restrict__ status) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     R fx = 0, fy = 0, fz = 0;
     for (int32_t s = ptr[i]; s < ptr[i + 1]; ++s) {
@@ -283,7 +284,7 @@ __global__ void k_clear_flag(int32_t *flag) {
 __global__ __launch_bounds__(256) void k_copy_weights(const double *__restrict__ src, int64_t E,
                                                       double *__restrict__ dst,
                                                       int32_t *__restrict__ bad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= 2 * E) return;
     const double w = src[i];
     if (!(w >= 0.0) || !isfinite(w)) atomicOr(bad, 1);

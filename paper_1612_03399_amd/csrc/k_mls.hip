@@ -49,6 +49,7 @@
 #include <cmath>
 
 #include "step_common.h"
+#include "xcd.h"
 
 namespace {
 
@@ -460,24 +461,14 @@ __device__ __forceinline__ void probe_face(
     if (bad) atomicOr(status, IP_STATUS_NONFINITE);
 }
 
-// Workgroups are dealt to the eight XCDs in turn (workgroup i to XCD i mod 8),
-// each XCD with its own L2.  This numbering gives XCD x one contiguous range
-// of the n logical blocks (its k-th workgroup takes block start_x + k), so
-// the consecutive faces of a body, whose probe ends read the same grid
-// points, are fetched into one L2 rather than into all eight.  A bijection
-// of 0 .. n - 1 whatever the hardware's order.
-__device__ __forceinline__ int64_t xcd_block() {
-    const int64_t n = gridDim.x, i = blockIdx.x;
-    const int64_t q = n / 8, r = n % 8, x = i % 8, k = i / 8;
-    return x * q + (x < r ? x : r) + k;
-}
-
 template <typename R>
 __global__ __launch_bounds__(256, 2) void k_probe_loads(
     const double *__restrict__ X, const int32_t *__restrict__ faces,
     const int64_t *__restrict__ face_off, const uint8_t *__restrict__ closed, int B, int64_t F,
     const R *__restrict__ u, const R *__restrict__ pr, const R *__restrict__ acc, MlsGrid g,
     double mu, R *__restrict__ Fext, uint32_t *status) {
+    // blocks in XCD-contiguous order: the faces of a body, whose probe ends
+    // read the same grid points, share an L2
     const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     // body of face f, the last b with face_off[b] <= f: one binary search for
     // the wave's first face on scalar registers (the wave's faces are
