@@ -13,6 +13,7 @@
 //   dL/du += dt h^3 spread(P)        (interpolation's adjoint is spreading)
 // F_s is linear in k_s, so F_s/k_s is the family's force at unit constant.
 #include "step_common.h"
+#include "xcd.h"
 
 namespace {
 
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(256) void k_edges_jvp(
     const double *__restrict__ cs0, const double *__restrict__ ks, const double *__restrict__ kb,
     const double *__restrict__ ew, const double *__restrict__ P, double *__restrict__ slots,
     double *__restrict__ dotE) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int b = body_of(edge_off, B, e);
     const double ws = ew ? ew[2 * e] : 1.0, wb = ew ? ew[2 * e + 1] : 1.0;
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(256) void k_faces_jvp(
     const double *__restrict__ dV, const uint8_t *__restrict__ closed,
     const double *__restrict__ kA, const double *__restrict__ kV, const double *__restrict__ P,
     double *__restrict__ slots, double *__restrict__ dotF) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const int b = body_of(face_off, B, f);
     const int32_t *t = faces + 3 * f;
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_faces_jvp(
 // Node gather of the tangent slots (same lists as the forward gather).
 __global__ void k_gather_f64(const int32_t *__restrict__ ptr, const int32_t *__restrict__ ids,
                              const double *__restrict__ slots, int64_t N, double *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double fx = 0, fy = 0, fz = 0;
     for (int32_t s = ptr[i]; s < ptr[i + 1]; ++s) {
@@ -161,7 +162,7 @@ __global__ void k_gather_f64(const int32_t *__restrict__ ptr, const int32_t *__r
 // P = M lam' (pinned rows zeroed)
 __global__ void k_mask(const double *__restrict__ lam, const uint8_t *__restrict__ pinned,
                        int64_t N, double *__restrict__ P) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= 3 * N) return;
     P[i] = pinned[i / 3] ? 0.0 : lam[i];
 }
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(256) void k_lambda(const double *__restrict__ X,
                                                 const double *__restrict__ mass, int64_t N, int nx,
                                                 int ny, int nz, double inv_h, double dt,
                                                 double *__restrict__ lam_out) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t l = xcd_block() * blockDim.x + threadIdx.x;
     if (l >= N) return;
     const int b = body_of(node_off, B, l);
     const double c = dt * dt / mass[b];
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256) void k_interp_vjp_x(const double *__restrict__
                                                       const double *__restrict__ dU, int64_t N,
                                                       int nx, int ny, int nz, double inv_h,
                                                       double *__restrict__ gX) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t l = xcd_block() * blockDim.x + threadIdx.x;
     if (l >= N) return;
     double g[3];
     interp_grad_dot(ldX(X, l), ldX(dU, l), u, nx, ny, nz, inv_h, g);

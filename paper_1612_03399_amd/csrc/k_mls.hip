@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_interp_mls(const double *__restrict__ X
                                                     const int32_t *__restrict__ faces, int64_t F,
                                                     const R *__restrict__ u, MlsGrid g,
                                                     R *__restrict__ U, uint32_t *status) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= F) return;
     bool bad = false;
     double area;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_spread_mls(const double *__restrict__ X
                                                     const int32_t *__restrict__ faces, int64_t F,
                                                     const R *__restrict__ Fm, MlsGrid g,
                                                     R *__restrict__ fld, uint32_t *status) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
@@ -355,7 +355,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_direct_forcing_mls(
     const double *__restrict__ X, const int32_t *__restrict__ faces, int64_t F,
     const R *__restrict__ u, const R *__restrict__ Vb, MlsGrid g, double inv_dt, R *__restrict__ Fout, R *__restrict__ fld, uint32_t *status) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= F) return;
     double area;
     const vec3<double> x = centroid(X, faces, f, area);
@@ -942,7 +942,7 @@ __global__ __launch_bounds__(256) void k_centroid_to_nodes(const int32_t *__rest
                                                            int64_t N, int64_t E4,
                                                            const R *__restrict__ Fc,
                                                            R *__restrict__ Fn) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = xcd_block() * blockDim.x + threadIdx.x;
     if (n >= N) return;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = ptr[n]; q < ptr[n + 1]; ++q) {

@@ -2,6 +2,7 @@
 // regularised delta (27-point support, Section 2.2 of Spandan et al.) and the
 // explicit node update (Section 2.3).
 #include "ipibm_internal.h"
+#include "xcd.h"
 
 namespace {
 
@@ -48,7 +49,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_interp(const double *__restrict__ X,
                                                 const R *__restrict__ u, int64_t N, GridArgs g,
                                                 R *__restrict__ U) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t l = xcd_block() * blockDim.x + threadIdx.x;
     if (l >= N) return;
     const vec3<double> x = ldX(X, l);
 #pragma unroll
@@ -76,7 +77,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_spread(const double *__restrict__ X,
                                                 const R *__restrict__ Fn, int64_t N, GridArgs g,
                                                 R inv_h3, R *__restrict__ f) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t l = xcd_block() * blockDim.x + threadIdx.x;
     if (l >= N) return;
     const vec3<double> x = ldX(X, l);
 #pragma unroll
@@ -104,7 +105,7 @@ __global__ void k_update(double *__restrict__ X, const R *__restrict__ U,
                          const R *__restrict__ Fn, const uint8_t *__restrict__ pinned,
                          const int64_t *__restrict__ node_off, int B,
                          const double *__restrict__ mass, int64_t N, double dt) {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t l = xcd_block() * blockDim.x + threadIdx.x;
     if (l >= N || pinned[l]) return;
     const int b = body_of(node_off, B, l);
     const double c = dt * dt / mass[b];
